@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the MCLAHE hot path on one MI355X.
+
+Workload (default): 4D float32 photoemission-like volume (k_x, k_y, E, t) =
+256x256x128x32, kernel 32x32x16x8, 512 bins, clip limit 0.02, global
+histogram range; synthetic data from paper_1906_11355_amd.synth (seed 3).
+
+A step is one full pass of the hot path on that volume, inputs resident in
+HBM: range -> per-kernel histograms -> clip/CDF/LUT -> 2^D-corner
+interpolation (mclahe_run).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--mode global|kernel]
+                    [--no-cpu-baseline] [--calib-copy] [--batched]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, published peak
+METRIC = "Gvoxel/s + %HBM roofline, 4D fp32 MCLAHE; batched vs plain; serving p50/p99"
+SHAPE = (256, 256, 128, 32)
+KSIZE = (32, 32, 16, 8)
+NBINS = 512
+CLIP = 0.02
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_1906_11355_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(mode: str, pass_name: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if current."""
+    path = os.path.join(HERE, "profiles", f"traffic_{pass_name}_cfg3_{mode}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != kernel_source_hash():
+        return None           # kernel changed since the counters were taken
+    return d.get("hbm_bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="global", choices=["global", "kernel"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the mixed-batch persistent launch vs plain launches")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed "
+                                   "(see DESIGN.md) but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1906_11355_amd import _lib, synth
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    x = synth.gen_4d(SHAPE, 3)
+    t_gen = time.perf_counter() - t_gen
+    xt = torch.from_numpy(x).to(dev)
+    out = torch.empty_like(xt)
+    plan = _lib.Plan(SHAPE, KSIZE, NBINS, CLIP, args.mode, in_dtype="float32", out_dtype="float32")
+    ws = torch.empty(plan.workspace_size(), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    ptrs = (xt.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), stream)
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        plan.run_ptr(*ptrs)
+    torch.cuda.synchronize()
+    timer = _lib.Timer(max(1, args.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        timer.run(plan, *ptrs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    passes = timer.read()
+    ms = (t1 - t0) / max(1, args.steps) * 1e3
+    V = int(np.prod(SHAPE))
+    S_in = S_out = 4
+    value = V / (ms * 1e-3) / 1e9
+
+    # algorithmic bytes per launch of each pass (what the method must move)
+    alg = {"range": V * S_in, "hist": V * S_in, "map": V * (S_in + S_out)}
+    dom = max(alg, key=lambda k: passes[k])
+    achieved = alg[dom] / (passes[dom] * 1e-3) / 1e9
+    traffic = read_traffic(args.mode, dom)
+    path_bytes = V * (3 * S_in + S_out)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gvoxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"4d_photoemission_f32_{'x'.join(map(str, SHAPE))}"
+                               f"_kernel{'x'.join(map(str, KSIZE))}_bins{NBINS}_clip{CLIP}_{args.mode}",
+                   "global_batch": 1, "parallelism": "single_gpu"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "pass_ms": {k: round(passes[k], 4) for k in ("range", "hist", "clip", "map")},
+        "path_roofline": {"alg_bytes_per_step": path_bytes,
+                          "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
+                          "frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "input_gen_s": round(t_gen, 1),
+    }
+
+    if args.batched:
+        res["batched"] = bench_batched(torch, np, _lib, synth, dev)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t = time.perf_counter()
+        r = oracle.run(x, KSIZE, NBINS, CLIP, oracle.GLOBAL if args.mode == "global" else oracle.KERNEL)
+        dt = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": round(V / dt / 1e9, 5), "unit": "Gvoxel/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"the full {'x'.join(map(str, SHAPE))} volume, one step ({dt:.1f} s)"}
+        g = out.cpu().numpy()
+        res["parity_vs_oracle"] = {"max_abs_out": float(np.abs(g.astype(np.float64) - r["out"]).max())}
+    print(json.dumps(res), flush=True)
+
+
+def bench_batched(torch, np, _lib, synth, dev, n=None):
+    """Mixed batch: one persistent launch vs plain per-volume launches."""
+    specs = synth.mix_spec(64, 4)
+    if n:
+        specs = specs[:n]
+    items = [synth.gen_item(s) for s in specs]
+    xs = [torch.from_numpy(it.x).to(dev) for it in items]
+    plans = [_lib.Plan(it.x.shape, it.kernel_size, it.n_bins, it.clip_limit,
+                       "kernel" if it.adaptive else "global", in_dtype=str(it.x.dtype),
+                       out_dtype="float32") for it in items]
+    outs_b = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in xs]
+    outs_p = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in xs]
+    wsb = torch.empty(_lib.batched_workspace_size(plans), dtype=torch.uint8, device=dev)
+    wsp = [torch.empty(p.workspace_size(), dtype=torch.uint8, device=dev) for p in plans]
+    st = torch.cuda.current_stream(dev).cuda_stream
+    vox = sum(int(x.numel()) for x in xs)
+
+    def plain():
+        for p, x, o, w in zip(plans, xs, outs_p, wsp):
+            p.run_ptr(x.data_ptr(), o.data_ptr(), w.data_ptr(), w.numel(), st)
+
+    def batched():
+        _lib.run_batched_ptr(plans, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs_b],
+                             wsb.data_ptr(), wsb.numel(), st)
+
+    def timeit(f, k=10):
+        f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / k * 1e3
+
+    ms_p, ms_b = timeit(plain), timeit(batched)
+    same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_p))
+    return {"volumes": len(xs), "voxels": vox, "plain_ms": round(ms_p, 3), "batched_ms": round(ms_b, 3),
+            "plain_Gvox_s": round(vox / ms_p / 1e6, 2), "batched_Gvox_s": round(vox / ms_b / 1e6, 2),
+            "bit_identical": bool(same)}
+
+
+if __name__ == "__main__":
+    main()

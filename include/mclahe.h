@@ -1,0 +1,222 @@
+/*
+ * mclahe.h -- C ABI of the MI355X (gfx950) multidimensional CLAHE library.
+ *
+ * Multidimensional contrast limited adaptive histogram equalisation (MCLAHE,
+ * Stimper, Bauer, Ernstorfer, Schoelkopf and Xian, 2019).  The method takes
+ * an N-dimensional array, a kernel size per dimension, a number of histogram
+ * bins, a clip limit normalised to [0, 1] and a choice of global or adaptive
+ * (per-kernel) histogram range (Algorithm 1 and Sec. III.D), and computes:
+ *
+ *   1. the padding of Eq. 1 and its split of Eq. 2, as virtual symmetric
+ *      (edge-repeating) padding; nothing is materialised;
+ *   2. per-kernel histograms over the padded kernel grid (Alg. 1);
+ *   3. clipping with equal redistribution of the excess (Alg. 1);
+ *   4. the inclusive CDF, min-max normalised, as a per-kernel mapping table
+ *      (LUT) (Alg. 1, Sec. III.C);
+ *   5. Lagrange multilinear interpolation of the 2^D neighbouring kernels'
+ *      mappings at every voxel (Sec. III.C).
+ *
+ * Readings of points the paper leaves open, identical to the test oracle:
+ *   - Eq. 1 with the minus sign: p = 2b - 1 - ((s - 1) mod b), split
+ *     p0 = p / 2 before, p1 = (p + 1) / 2 after; kernel_size[i] <= shape[i];
+ *   - symmetric padding repeats the edge sample ([a b c] -> [b a|a b c|c b]);
+ *   - bin of value v in single precision, no contraction:
+ *       scale = (float)n_bins / (hi - lo);   t = (v - lo) * scale;
+ *       bin = !(t > 0) ? 0 : (t >= n_bins ? n_bins - 1 : (int)t);
+ *     (for hi == lo, scale is +inf and this gives v > lo ? n_bins-1 : 0);
+ *   - global range = min and max of the input, unless the caller gives one;
+ *     adaptive range = min and max over the kernel's padded voxels;
+ *   - clip count C = floor((double)clip_limit * K), K = prod(kernel_size);
+ *     excess E = sum_j max(h_j - C, 0) shared equally by all bins once; the
+ *     library keeps it exact in units of 1/n_bins count:
+ *       H_j = n_bins * min(h_j, C) + E;
+ *   - LUT_j = (float)((double)(cdf_j - cdf_0) / (double)(cdf_last - cdf_0))
+ *     with the inclusive cdf of H; a zero denominator gives j / (n_bins - 1);
+ *   - kernel centres at k*b + (b-1)/2 in padded coordinates; a voxel x lies
+ *     in the interpolation cell c = floor(m / 2b), m = 2(x + p0) - (b - 1),
+ *     with weight (m - 2bc) / 2b towards kernel c + 1;
+ *   - each of the 2^D kernels maps the voxel through its own LUT at the bin
+ *     of the voxel under that kernel's range; contributions are summed;
+ *   - float output lies in [0, 1]; u8/u16 output is
+ *     min(M, floor(y * M + 0.5)) in single precision, M = 255 or 65535.
+ *
+ * Precision: histograms and clipped counts are exact integers; LUTs are
+ * rounded once from double; the interpolated value is accumulated in float
+ * (|error| <= 1e-5 of full scale), integer output within one level.
+ *
+ * Memory and ownership.  The caller owns every device buffer: input, output
+ * and a workspace of mclahe_workspace_size() bytes (256-byte aligned).  The
+ * library never allocates device memory in mclahe_run or mclahe_run_batched;
+ * mclahe_plan allocates host memory only.  Arrays are C-contiguous, last axis
+ * fastest.  Input and output may alias only if their element sizes match.
+ * All run calls are asynchronous on the given HIP stream (NULL = the default
+ * stream); a kernel fault surfaces at the caller's next synchronisation.
+ *
+ * Errors.  Every function returns an mclahe_status; no exception crosses the
+ * ABI.  mclahe_last_error() returns a thread-local message describing the
+ * last failure on the calling thread.
+ */
+#ifndef MCLAHE_H_
+#define MCLAHE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCLAHE_SUCCESS = 0,
+    MCLAHE_ERROR_INVALID_VALUE = 1,  /* bad argument (null, range, shape)      */
+    MCLAHE_ERROR_NOT_SUPPORTED = 2,  /* valid but outside this build's limits  */
+    MCLAHE_ERROR_OUT_OF_MEMORY = 3,  /* host allocation failed                 */
+    MCLAHE_ERROR_WORKSPACE = 4,      /* workspace too small or misaligned      */
+    MCLAHE_ERROR_HIP = 5             /* a HIP runtime call failed              */
+} mclahe_status;
+
+typedef enum { MCLAHE_U8 = 0, MCLAHE_U16 = 1, MCLAHE_F32 = 2 } mclahe_dtype;
+
+/* Global histogram range (GHR) or adaptive, per-kernel range (AHR), Sec. III.D */
+typedef enum { MCLAHE_RANGE_GLOBAL = 0, MCLAHE_RANGE_KERNEL = 1 } mclahe_range_mode;
+
+typedef struct mclahe_plan_s *mclahe_plan_t;
+
+/* Byte offsets into the workspace of the per-plan intermediate arrays, so
+ * that tests can read them back.  N_k = number of kernels of the padded grid
+ * (row-major over the kernel grid, last axis fastest), n = n_bins.
+ *   hist    : u32 [N_k][n]   per-kernel histograms
+ *   clipped : u64 [N_k][n]   H = n*min(h, C) + E (clip step, units of 1/n)
+ *   lut     : f32 [N_k][n]   normalised CDF maps
+ *   range   : f32 [N_k][2] (AHR) or [2] (GHR), lo then hi
+ *   scale   : f32 [N_k] (AHR) or [1] (GHR), (float)n / (hi - lo)
+ *   total   : bytes needed                                                  */
+typedef struct {
+    uint64_t hist, clipped, lut, range, scale, total;
+} mclahe_layout;
+
+/* Geometry of a plan, for inspection: per axis the padding p (Eq. 1), its
+ * split p0/p1 (Eq. 2) and the number of kernels n = (s + p) / b; K = voxels
+ * per kernel; clip_count = C; n_kernels = N_k; n_cells = number of
+ * interpolation cells (prod(n_i - 1)).                                      */
+typedef struct {
+    int32_t ndim;
+    int64_t pad[8], pad0[8], pad1[8], n_kernels_axis[8];
+    int64_t n_kernels, kernel_voxels, clip_count, n_voxels, n_cells;
+} mclahe_geometry;
+
+/* Work decomposition knobs.  Any setting yields bit-identical results; only
+ * speed changes.  Zero fields mean "library default".
+ *   hist_rows_split   : row chunks per kernel column in the histogram pass
+ *   hist_copies       : LDS histogram replicas (1, 2, 4, 8) against bin collisions
+ *   hist_peel         : wavefront aggregation of colliding bins: 1 = off,
+ *                       2 = one round, 3 = two rounds (0 = default)
+ *   map_rows_split    : row chunks per cell column in the interpolation pass
+ *   map_group         : interpolation cells per work unit along the last axis
+ *   persistent_blocks : grid size of the persistent batched kernel          */
+typedef struct {
+    int32_t hist_rows_split, hist_copies, hist_peel;
+    int32_t map_rows_split, map_group;
+    int32_t persistent_blocks;
+} mclahe_tuning;
+
+/* Create a plan (host only; no device call).  Arguments follow the paper's
+ * statement of the problem (Alg. 1 inputs and parameters; Sec. III.D):
+ *   ndim         : 1..8
+ *   shape        : ndim sizes s_i >= 1 (total voxels < 2^40)
+ *   kernel_size  : ndim sizes 1 <= b_i <= s_i; prod(b) < 2^32
+ *   n_bins       : 2..8192
+ *   clip_limit   : finite, >= 0 (>= 1 disables clipping, 0 = uniform)
+ *   mode         : MCLAHE_RANGE_GLOBAL or MCLAHE_RANGE_KERNEL
+ *   user_range   : NULL, or {lo, hi} finite with lo < hi (GLOBAL only)
+ *   in_dtype     : u8, u16 or f32 (f32 input must be finite)
+ *   out_dtype    : f32 (values in [0,1]) or u8/u16 codes
+ * Returns INVALID_VALUE for arguments outside these ranges.                 */
+mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape,
+                          const int64_t *kernel_size, int n_bins, float clip_limit,
+                          mclahe_range_mode mode, const float *user_range,
+                          mclahe_dtype in_dtype, mclahe_dtype out_dtype);
+
+/* Release a plan (NULL is accepted).                                        */
+mclahe_status mclahe_plan_destroy(mclahe_plan_t plan);
+
+/* Geometry of Eq. 1-2 and the kernel grid for a plan.                       */
+mclahe_status mclahe_plan_geometry(mclahe_plan_t plan, mclahe_geometry *geom);
+
+/* Read or replace the plan's work decomposition.  Changing it changes the
+ * workspace size; results stay bit-identical.  Not thread-safe against
+ * concurrent runs of the same plan.                                         */
+mclahe_status mclahe_plan_get_tuning(mclahe_plan_t plan, mclahe_tuning *tuning);
+mclahe_status mclahe_plan_set_tuning(mclahe_plan_t plan, const mclahe_tuning *tuning);
+
+/* Workspace bytes for mclahe_run with the plan's current tuning.            */
+mclahe_status mclahe_workspace_size(mclahe_plan_t plan, size_t *bytes);
+
+/* Offsets of the intermediate arrays inside the workspace (see above).     */
+mclahe_status mclahe_workspace_layout(mclahe_plan_t plan, mclahe_layout *layout);
+
+/* Enhance one volume: d_in -> d_out, all four passes enqueued on hip_stream
+ * (range, histogram, clip/CDF/LUT, interpolation).  d_workspace must be
+ * 256-byte aligned and hold workspace_bytes >= mclahe_workspace_size();
+ * d_in/d_out must be aligned to their element size (16 bytes enables wide
+ * loads).  Returns WORKSPACE if the workspace is too small or misaligned. */
+mclahe_status mclahe_run(mclahe_plan_t plan, const void *d_in, void *d_out,
+                         void *d_workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Workspace bytes for a batched call over n plans (sum of the per-volume
+ * workspaces plus the work-queue header and descriptor table).             */
+mclahe_status mclahe_batched_workspace_size(int n, const mclahe_plan_t *plans, size_t *bytes);
+
+/* Per-volume workspace offsets inside a batched workspace: offsets[i] is the
+ * byte offset of volume i's own workspace (laid out as mclahe_workspace_layout
+ * of plans[i]).                                                             */
+mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans,
+                                               uint64_t *offsets);
+
+/* Enhance n independent volumes (mixed ndim, shape, dtype, parameters) with
+ * ONE persistent fused kernel launch, replayed from a cached hipGraph.  Each
+ * output is bit-identical to mclahe_run of the same plan.  The plans must
+ * stay alive until the work has completed on the stream.                    */
+mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans,
+                                 const void *const *d_in, void *const *d_out,
+                                 void *d_workspace, size_t workspace_bytes,
+                                 void *hip_stream);
+
+/* Autotune the plan's work decomposition on the current device: times the
+ * candidate settings on the given buffers (which it overwrites) and keeps
+ * the fastest.  Needs workspace_bytes >= mclahe_autotune_workspace_size().
+ * Synchronises hip_stream.  Results are cached per problem class in memory
+ * and, if the environment variable MCLAHE_TUNE_CACHE names a file, there. */
+mclahe_status mclahe_autotune_workspace_size(mclahe_plan_t plan, size_t *bytes);
+mclahe_status mclahe_autotune(mclahe_plan_t plan, const void *d_in, void *d_out,
+                              void *d_workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Per-pass timing for benchmarks.  A timer holds HIP events for up to
+ * max_runs calls; mclahe_run_timed is mclahe_run that also records an event
+ * before each of the four passes and after the last (no synchronisation).
+ * mclahe_timer_read synchronises on the last event and returns, per pass
+ * (range, histogram, clip/CDF/LUT, interpolation), the mean milliseconds over
+ * the recorded runs, and the number of runs; mclahe_timer_reset forgets them.
+ * Calls past max_runs return INVALID_VALUE.                                 */
+typedef struct mclahe_timer_s *mclahe_timer_t;
+mclahe_status mclahe_timer_create(mclahe_timer_t *timer, int max_runs);
+mclahe_status mclahe_timer_destroy(mclahe_timer_t timer);
+mclahe_status mclahe_timer_reset(mclahe_timer_t timer);
+mclahe_status mclahe_run_timed(mclahe_plan_t plan, const void *d_in, void *d_out, void *d_workspace,
+                               size_t workspace_bytes, void *hip_stream, mclahe_timer_t timer);
+mclahe_status mclahe_timer_read(mclahe_timer_t timer, float *pass_ms, int *runs);
+
+/* Human-readable name of a status code (static storage).                   */
+const char *mclahe_status_string(mclahe_status s);
+
+/* Thread-local message for the last failure on this thread ("" if none).   */
+const char *mclahe_last_error(void);
+
+/* Library version, e.g. "0.1.0".                                            */
+const char *mclahe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCLAHE_H_ */

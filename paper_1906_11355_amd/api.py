@@ -1,0 +1,103 @@
+"""PyTorch-facing entry points: tensors in, tensors out, on the current stream.
+
+PyTorch only supplies device memory and streams; the work is done by the
+library's HIP kernels through the C ABI (see ``_lib``).
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import F32, KERNEL, U8, U16, Plan
+
+TORCH_DTYPE = {U8: torch.uint8, U16: torch.uint16, F32: torch.float32}
+
+
+def stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def plan_for(x: torch.Tensor, kernel_size: Sequence[int], n_bins: int = 256, clip_limit: float = 0.01,
+             mode="global", user_range=None, out_dtype=torch.float32) -> Plan:
+    return Plan(tuple(x.shape), kernel_size, n_bins, clip_limit, mode, user_range,
+                in_dtype=x.dtype, out_dtype=out_dtype)
+
+
+def _check_tensor(x: torch.Tensor, name: str):
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def enhance(x: torch.Tensor, kernel_size: Sequence[int], n_bins: int = 256, clip_limit: float = 0.01,
+            mode="global", user_range=None, out_dtype=torch.float32, plan: Plan | None = None,
+            workspace: torch.Tensor | None = None, out: torch.Tensor | None = None,
+            return_workspace: bool = False):
+    """Multidimensional CLAHE of one volume (asynchronous on the current stream)."""
+    _check_tensor(x, "input")
+    if plan is None:
+        plan = plan_for(x, kernel_size, n_bins, clip_limit, mode, user_range, out_dtype)
+    need = plan.workspace_size()
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    if out is None:
+        out = torch.empty(x.shape, dtype=TORCH_DTYPE[plan.out_code], device=x.device)
+    _check_tensor(out, "output")
+    plan.run_ptr(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                 stream_handle(x.device))
+    return (out, workspace, plan) if return_workspace else out
+
+
+def read_workspace(plan: Plan, ws: torch.Tensor, base: int = 0) -> dict:
+    """Views of the intermediate arrays (hist, clipped, lut, range, scale)."""
+    lay = plan.layout()
+    g = plan.geometry()
+    nk, nb = g["n_kernels"], plan.n_bins
+    ahr = plan.mode == KERNEL
+
+    def view(off, count, dtype, esize):
+        return ws[base + off: base + off + count * esize].view(dtype)
+
+    return dict(
+        hist=view(lay["hist"], nk * nb, torch.int32, 4).view(nk, nb),
+        clipped=view(lay["clipped"], nk * nb, torch.int64, 8).view(nk, nb),
+        lut=view(lay["lut"], nk * nb, torch.float32, 4).view(nk, nb),
+        range=view(lay["range"], (nk * 2 if ahr else 2), torch.float32, 4).view(-1, 2) if ahr
+        else view(lay["range"], 2, torch.float32, 4),
+        scale=view(lay["scale"], nk if ahr else 1, torch.float32, 4),
+    )
+
+
+def make_plans(xs: Sequence[torch.Tensor], params: Sequence[dict]) -> list:
+    return [plan_for(x, **p) for x, p in zip(xs, params)]
+
+
+def enhance_batched(xs: Sequence[torch.Tensor], params: Sequence[dict] | None = None, plans=None,
+                    outs=None, workspace: torch.Tensor | None = None, return_workspace: bool = False):
+    """Enhance many volumes with one persistent fused launch (hipGraph)."""
+    if plans is None:
+        plans = make_plans(xs, params)
+    for x in xs:
+        _check_tensor(x, "input")
+    need = _lib.batched_workspace_size(plans)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=xs[0].device)
+    if outs is None:
+        outs = [torch.empty(x.shape, dtype=TORCH_DTYPE[p.out_code], device=x.device)
+                for x, p in zip(xs, plans)]
+    _lib.run_batched_ptr(plans, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs],
+                         workspace.data_ptr(), workspace.numel(), stream_handle(xs[0].device))
+    return (outs, workspace, plans) if return_workspace else outs
+
+
+def autotune(plan: Plan, x: torch.Tensor, out: torch.Tensor | None = None):
+    """Pick the fastest work decomposition for this plan on the current GPU."""
+    _check_tensor(x, "input")
+    ws = torch.empty(plan.autotune_workspace_size(), dtype=torch.uint8, device=x.device)
+    if out is None:
+        out = torch.empty(x.shape, dtype=TORCH_DTYPE[plan.out_code], device=x.device)
+    plan.autotune_ptr(x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), stream_handle(x.device))
+    return plan.tuning()

@@ -1,0 +1,141 @@
+// Volume descriptor and geometry helpers shared by the host runtime and the
+// gfx950 kernels of the MCLAHE library.  Plain-old-data only: the same struct
+// is passed by value to the per-pass kernels and stored in a device table for
+// the persistent batched kernel.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define MC_HD __host__ __device__ __forceinline__
+#else
+#define MC_HD inline
+#endif
+
+#define MC_MAXD 8          // dimensions supported
+#define MC_T 256           // threads per work-group (4 wavefronts of 64)
+#define MC_OMAX 256        // outer-row table entries per work unit
+#define MC_LDS_BUDGET (64 * 1024)   // LDS a work unit may use (bytes)
+#define MC_NUM_CU 256      // MI355X compute units (tiling target)
+
+enum { MC_U8 = 0, MC_U16 = 1, MC_F32 = 2 };
+enum { MC_GHR = 0, MC_AHR = 1 };
+
+// One axis of the padded kernel grid: size s, kernel b, padding p0 before and
+// p1 after (Eq. 1-2), n = (s + p0 + p1) / b kernels.
+struct McAxis {
+    int32_t s, b, p0, p1, n;
+};
+
+// Original-coordinate footprint of kernel k along one axis: every padded
+// position of the kernel mirrors to an x in [lo, hi); x in [olo, ohi) is hit
+// twice (once directly, once through the mirror), every other x once.
+struct McBox {
+    int32_t lo, hi, olo, ohi;
+};
+
+MC_HD int32_t mc_min(int32_t a, int32_t b) { return a < b ? a : b; }
+MC_HD int32_t mc_max(int32_t a, int32_t b) { return a > b ? a : b; }
+
+MC_HD McBox mc_kernel_box(const McAxis &a, int32_t k)
+{
+    const int32_t q0 = k * a.b, q1 = q0 + a.b;
+    // direct part: q in [max(q0,p0), min(q1,p0+s)) -> x = q - p0
+    const int32_t d0 = mc_max(q0, a.p0) - a.p0, d1 = mc_min(q1, a.p0 + a.s) - a.p0;
+    // mirrored part (a window of b <= s voxels holds at most one fold)
+    int32_t m0 = 0, m1 = 0;
+    if (q0 < a.p0) {                       // start fold: x = p0 - 1 - q
+        m0 = a.p0 - mc_min(q1, a.p0);
+        m1 = a.p0 - q0;
+    } else if (q1 > a.p0 + a.s) {          // end fold: x = 2s - 1 - (q - p0)
+        m0 = 2 * a.s + a.p0 - q1;
+        m1 = 2 * a.s + a.p0 - mc_max(q0, a.p0 + a.s);
+    }
+    McBox r;
+    const bool hd = d0 < d1, hm = m0 < m1;
+    r.lo = hd ? (hm ? mc_min(d0, m0) : d0) : m0;
+    r.hi = hd ? (hm ? mc_max(d1, m1) : d1) : m1;
+    r.olo = mc_max(d0, m0);
+    r.ohi = mc_min(d1, m1);
+    if (!(hd && hm) || r.olo >= r.ohi) r.olo = r.ohi = r.lo;
+    return r;
+}
+
+// Multiplicity (0, 1 or 2) of original coordinate x in kernel k's footprint.
+MC_HD int32_t mc_mult(const McBox &bx, int32_t x)
+{
+    return (x >= bx.lo && x < bx.hi) ? 1 + (x >= bx.olo && x < bx.ohi) : 0;
+}
+
+// Interpolation cell c (voxels whose lower neighbour kernel is c) along one
+// axis: x in [lo, hi).  Kernel centres sit at k*b + (b-1)/2 in padded
+// coordinates, so the cell starts at b*c + floor(b/2) - p0.
+MC_HD void mc_cell_range(const McAxis &a, int32_t c, int32_t &lo, int32_t &hi)
+{
+    lo = a.b * c + a.b / 2 - a.p0;
+    hi = lo + a.b;
+    if (lo < 0) lo = 0;
+    if (hi > a.s) hi = a.s;
+}
+
+// Doubled offset of x from the lower kernel centre of its cell c:
+// m = 2(x + p0) - (b - 1) - 2bc, in [0, 2b); weight = m / (2b).
+MC_HD int32_t mc_cell_m(const McAxis &a, int32_t c, int32_t x)
+{
+    return 2 * (x + a.p0) - (a.b - 1) - 2 * a.b * c;
+}
+
+// Everything the kernels need about one volume.
+struct McVol {
+    // ---- problem -----------------------------------------------------------
+    int32_t D, nb, in_dt, out_dt, mode, has_user_range;
+    float user_lo, user_hi;
+    int64_t clipC;            // clip count C = floor(clip * K)
+    int64_t K;                // voxels per kernel
+    McAxis ax[MC_MAXD];
+    int64_t stride[MC_MAXD];  // element strides (C-contiguous)
+    int64_t nvox, nker;
+    int32_t vec;              // elements per vector chunk (1 or 16/sizeof(in))
+    int32_t path;             // 0 = LDS-staged fast map, 1 = generic map
+    // ---- histogram / adaptive-range work units ------------------------------
+    int32_t hG, hP, hS, hCr;  // kernels per segment, parts per kernel,
+                              // segments on the last axis, row chunks
+    int32_t hR, hPeel;        // LDS replicas, aggregation rounds
+    int64_t hCols;            // kernel columns (prod of n_i, i < D-1)
+    uint32_t n_hist_wu;       // hCols * hS * hCr
+    uint32_t n_range_wu;      // GHR min/max blocks (0 if a user range is given)
+    // ---- interpolation work units -------------------------------------------
+    int32_t mG, mS, mCr, mP;  // cells per group, segments on the last axis,
+                              // row chunks, parts per cell (mP > 1: mG = 1)
+    int64_t mCols;            // cell columns (prod of n_i - 1, i < D-1)
+    uint32_t n_map_wu;        // mCols * mS * mCr
+    uint32_t n_clip_wu;       // = nker
+    // ---- buffers -------------------------------------------------------------
+    const void *in;
+    void *out;
+    uint32_t *part;           // [n_hist_wu][hG][nb]   partial histograms
+    float *rpart;             // GHR: [n_range_wu][2]; AHR: [n_hist_wu][hG][2]
+    uint32_t *hist;           // [nker][nb]
+    unsigned long long *clipped;  // [nker][nb]
+    float *lut;               // [nker][nb]
+    float *range;             // GHR: [2]; AHR: [nker][2]
+    float *scale;             // GHR: [1]; AHR: [nker]
+};
+
+// Header of the persistent batched kernel's work queue (device memory).
+// Tickets are handed out in phase-major order: all range units of all
+// volumes, then all histogram units, then clip units, then map units.
+#define MC_PHASES 4
+struct McQueue {
+    uint32_t head;                 // next ticket
+    uint32_t error;                // set if a bounded wait expired
+    uint32_t pad_[2];
+};
+
+// Device table: header, per-phase per-volume ticket prefix sums, volumes.
+struct McBatch {
+    uint32_t nvol, total;
+    uint32_t phase_start[MC_PHASES + 1];
+    uint32_t spin_limit;
+    uint32_t pad_;
+};

@@ -1,0 +1,1083 @@
+// gfx950 device code of the MCLAHE library.
+//
+// Every pass is written as a "work unit" device function that a work-group of
+// MC_T = 256 threads (4 wave64s) executes.  The per-pass kernels launch one
+// work-group per unit; the persistent batched kernel pulls units of many
+// volumes from a queue and calls the very same functions, so both paths
+// produce bit-identical results.
+//
+// Passes (Algorithm 1 of Stimper et al.; Sec. III.C-D):
+//   range : global min/max (GHR) or per-kernel min/max (AHR)
+//   hist  : per-kernel histograms over the virtually padded kernel grid
+//   clip  : clip + equal redistribution (exact integers), inclusive CDF,
+//           min-max normalisation -> per-kernel LUT
+//   map   : 2^D-corner multilinear interpolation of the LUTs at every voxel
+//
+// Padding is never materialised.  A kernel's padded voxels mirror onto an
+// interval ("box") of original coordinates per axis, hit once or twice
+// (mc_kernel_box), so a histogram is accumulated over original voxels with
+// integer weights equal to the product of the per-axis multiplicities.  This
+// is exactly the count over the padded voxels, with each voxel read once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mc_desc.h"
+
+namespace mc {
+
+// ------------------------------------------------------------------ basics --
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Bin of v (single precision, no contraction; identical to the reading used
+// by the oracle; scale = +inf for a degenerate range gives 0 / n-1 as well).
+__device__ __forceinline__ int bin_of(float v, float lo, float scale, float nbf, int nbm1)
+{
+    const float t = (v - lo) * scale;
+    const int r = (t >= nbf) ? nbm1 : (int)t;
+    return (t > 0.0f) ? r : 0;
+}
+
+__device__ __forceinline__ float range_scale(int nb, float lo, float hi)
+{
+    return __fdiv_rn((float)nb, hi - lo);
+}
+
+// Ordered integer image of a float for atomic min/max in LDS.
+__device__ __forceinline__ int f2o(float f)
+{
+    const int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float o2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
+
+// V consecutive input elements (16-byte aligned when V > 1) as floats.
+template <typename Tin, int V>
+__device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)[V])
+{
+    if constexpr (V == 1) {
+        f[0] = (float)p[0];
+    } else {
+        static_assert(V * sizeof(Tin) == 16, "wide chunk is 16 bytes");
+        const uint4 q = *reinterpret_cast<const uint4 *>(p);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        if constexpr (sizeof(Tin) == 4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
+        } else if constexpr (sizeof(Tin) == 2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                f[2 * i] = (float)(w[i] & 0xffffu);
+                f[2 * i + 1] = (float)(w[i] >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                f[4 * i] = (float)(w[i] & 0xffu);
+                f[4 * i + 1] = (float)((w[i] >> 8) & 0xffu);
+                f[4 * i + 2] = (float)((w[i] >> 16) & 0xffu);
+                f[4 * i + 3] = (float)(w[i] >> 24);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
+{
+    if (dt == MC_U8) return (float)((const uint8_t *)in)[i];
+    if (dt == MC_U16) return (float)((const uint16_t *)in)[i];
+    return ((const float *)in)[i];
+}
+
+// Quantised or float store of one output value.
+__device__ __forceinline__ void store_elem(void *out, int dt, int64_t i, float y)
+{
+    if (dt == MC_F32) {
+        __builtin_nontemporal_store(y, (float *)out + i);
+    } else {
+        const float M = dt == MC_U8 ? 255.0f : 65535.0f;
+        float q = floorf(y * M + 0.5f);
+        q = fminf(fmaxf(q, 0.0f), M);
+        if (dt == MC_U8) ((uint8_t *)out)[i] = (uint8_t)q;
+        else ((uint16_t *)out)[i] = (uint16_t)q;
+    }
+}
+
+// Block-wide reductions over MC_T threads through LDS scratch of MC_T words.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
+                                                            unsigned long long *s)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = MC_T / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    const unsigned long long r = s[0];
+    __syncthreads();
+    return r;
+}
+
+// Exclusive prefix sum over the block (Hillis-Steele in LDS).
+__device__ __forceinline__ unsigned long long block_exscan_u64(unsigned long long v,
+                                                               unsigned long long *s)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < MC_T; o <<= 1) {
+        const unsigned long long a = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        s[threadIdx.x] += a;
+        __syncthreads();
+    }
+    const unsigned long long r = s[threadIdx.x] - v;
+    __syncthreads();
+    return r;
+}
+
+// ----------------------------------------------------------- row iteration --
+// A work unit covers a rectangular set of original voxels: an interval per
+// outer axis (0..D-2) and a segment [xs, xe) of the last axis.  Its rows (one
+// per outer coordinate tuple, last outer axis fastest) are split into
+// contiguous chunks.  Row coordinates are kept as (o, r) with r the index on
+// the innermost outer axis (D-2) and o the flattened index of axes 0..D-3,
+// whose offset and weight come from an LDS table built once per unit.
+struct RowSpace {
+    int32_t lo[MC_MAXD], len[MC_MAXD];   // interval per outer axis
+    int64_t rows;                         // product of len over outer axes
+    int32_t in_lo, in_len;                // innermost outer axis (or dummy)
+    int64_t in_stride;
+};
+
+__device__ __forceinline__ void rowspace_finish(const McVol &d, RowSpace &rs)
+{
+    const int D = d.D;
+    rs.rows = 1;
+    rs.in_lo = 0;
+    rs.in_len = 1;
+    rs.in_stride = 0;
+#pragma unroll
+    for (int i = 0; i < MC_MAXD - 1; ++i) {
+        if (i < D - 1) rs.rows *= rs.len[i];
+        if (i == D - 2) {
+            rs.in_lo = rs.lo[i];
+            rs.in_len = rs.len[i];
+            rs.in_stride = d.stride[i];
+        }
+    }
+}
+
+// Decode o (flattened axes 0..D-3) into coordinates; unrolled with guards so
+// that every array index is a compile-time constant (no scratch memory).
+__device__ __forceinline__ void decode_outer(const McVol &d, const RowSpace &rs, int64_t o,
+                                             int32_t (&x)[MC_MAXD])
+{
+    const int D = d.D;
+#pragma unroll
+    for (int i = MC_MAXD - 1; i >= 0; --i) {
+        if (i <= D - 3) {
+            const int64_t q = o / rs.len[i];
+            x[i] = rs.lo[i] + (int32_t)(o - q * rs.len[i]);
+            o = q;
+        }
+    }
+}
+
+// Segment j of the last axis for the histogram / adaptive-range units:
+// kernels [kA, kB) and original coordinates [xs, xe).
+__device__ __forceinline__ void hist_segment(const McVol &d, int j, int &kA, int &kB, int &xs,
+                                             int &xe)
+{
+    const McAxis &a = d.ax[d.D - 1];
+    if (d.hP == 1) {
+        kA = j * d.hG;
+        kB = mc_min(kA + d.hG, a.n);
+        xs = 0x7fffffff;
+        xe = -1;
+        for (int k = kA; k < kB; ++k) {
+            const McBox b = mc_kernel_box(a, k);
+            xs = mc_min(xs, b.lo);
+            xe = mc_max(xe, b.hi);
+        }
+    } else {
+        kA = j / d.hP;
+        kB = kA + 1;
+        const int pp = j - kA * d.hP;
+        const McBox b = mc_kernel_box(a, kA);
+        const int len = b.hi - b.lo;
+        xs = b.lo + (int)((int64_t)len * pp / d.hP);
+        xe = b.lo + (int)((int64_t)len * (pp + 1) / d.hP);
+    }
+}
+
+// Decode a histogram-unit index into its kernel column, segment and chunk,
+// and the row space of the column.
+__device__ __forceinline__ void hist_unit(const McVol &d, uint32_t wu, int64_t &col, int &seg,
+                                          int &chunk, RowSpace &rs, McBox (&obox)[MC_MAXD],
+                                          McBox &ib)
+{
+    ib = McBox{0, 1, 0, 0};
+    const int D = d.D;
+    chunk = (int)(wu % (uint32_t)d.hCr);
+    const uint32_t t1 = wu / (uint32_t)d.hCr;
+    seg = (int)(t1 % (uint32_t)d.hS);
+    col = (int64_t)(t1 / (uint32_t)d.hS);
+    int64_t c = col;
+#pragma unroll
+    for (int i = MC_MAXD - 2; i >= 0; --i) {
+        if (i <= D - 2) {
+            const int64_t q = c / d.ax[i].n;
+            const int k = (int)(c - q * d.ax[i].n);
+            c = q;
+            obox[i] = mc_kernel_box(d.ax[i], k);
+            rs.lo[i] = obox[i].lo;
+            rs.len[i] = obox[i].hi - obox[i].lo;
+            if (i == D - 2) ib = obox[i];
+        }
+    }
+    rowspace_finish(d, rs);
+}
+
+// Outer-row table for histogram units: element offset and integer weight of
+// every o in [o0, o0 + cnt).
+struct HistOTab {
+    int64_t off;
+    uint32_t w;
+    uint32_t pad_;
+};
+
+__device__ __forceinline__ void build_hist_otab(const McVol &d, const RowSpace &rs,
+                                                const McBox (&obox)[MC_MAXD], int64_t o0,
+                                                int cnt, HistOTab *tab)
+{
+    const int D = d.D;
+    for (int j = threadIdx.x; j < cnt; j += MC_T) {
+        int32_t x[MC_MAXD];
+        decode_outer(d, rs, o0 + j, x);
+        int64_t off = 0;
+        uint32_t w = 1;
+#pragma unroll
+        for (int i = 0; i < MC_MAXD; ++i) {
+            if (i <= D - 3) {
+                off += (int64_t)x[i] * d.stride[i];
+                w *= (uint32_t)mc_mult(obox[i], x[i]);
+            }
+        }
+        tab[j].off = off;
+        tab[j].w = w;
+    }
+}
+
+// ------------------------------------------------------------ range (GHR) --
+// Global min/max over the flat input: unit u covers a contiguous block.
+template <typename Tin, int V>
+__device__ void range_ghr_unit_v(const McVol &d, uint32_t u, float *red)
+{
+    const Tin *in = (const Tin *)d.in;
+    const int64_t nvec = d.nvox / V;
+    const int64_t per = (nvec + d.n_range_wu - 1) / d.n_range_wu;
+    const int64_t v0 = (int64_t)u * per, v1 = v0 + per < nvec ? v0 + per : nvec;
+    float mn = INFINITY, mx = -INFINITY;
+    int64_t i = v0 + threadIdx.x;
+    for (; i + 3 * MC_T < v1; i += 4 * MC_T) {
+        float f[4][V];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) load_chunk<Tin, V>(in + (i + k * MC_T) * V, f[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                mn = fminf(mn, f[k][e]);
+                mx = fmaxf(mx, f[k][e]);
+            }
+    }
+    for (; i < v1; i += MC_T) {
+        float f[V];
+        load_chunk<Tin, V>(in + i * V, f);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            mn = fminf(mn, f[e]);
+            mx = fmaxf(mx, f[e]);
+        }
+    }
+    if (u == d.n_range_wu - 1) {            // scalar tail of the last vector
+        for (int64_t t = nvec * V + threadIdx.x; t < d.nvox; t += MC_T) {
+            const float f = (float)in[t];
+            mn = fminf(mn, f);
+            mx = fmaxf(mx, f);
+        }
+    }
+    red[threadIdx.x] = mn;
+    red[MC_T + threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = MC_T / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[threadIdx.x] = fminf(red[threadIdx.x], red[threadIdx.x + o]);
+            red[MC_T + threadIdx.x] = fmaxf(red[MC_T + threadIdx.x], red[MC_T + threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.rpart[2 * u] = red[0];
+        d.rpart[2 * u + 1] = red[MC_T];
+    }
+}
+
+template <typename Tin>
+__device__ void range_ghr_unit(const McVol &d, uint32_t u, char *smem)
+{
+    constexpr int VM = 16 / sizeof(Tin);
+    if (d.vec == VM) range_ghr_unit_v<Tin, VM>(d, u, (float *)smem);
+    else range_ghr_unit_v<Tin, 1>(d, u, (float *)smem);
+}
+
+// Reduce the GHR partials (or take the user range); every unit that calls
+// this gets the same lo, hi and scale.
+__device__ __forceinline__ void ghr_range(const McVol &d, float *red, float &lo, float &hi,
+                                          float &scale)
+{
+    if (d.has_user_range) {
+        lo = d.user_lo;
+        hi = d.user_hi;
+    } else {
+        float mn = INFINITY, mx = -INFINITY;
+        for (uint32_t i = threadIdx.x; i < d.n_range_wu; i += MC_T) {
+            mn = fminf(mn, d.rpart[2 * i]);
+            mx = fmaxf(mx, d.rpart[2 * i + 1]);
+        }
+        int *ri = (int *)red;
+        if (threadIdx.x == 0) {
+            ri[0] = 0x7fffffff;
+            ri[1] = (int)0x80000000;
+        }
+        __syncthreads();
+        atomicMin(&ri[0], f2o(mn));
+        atomicMax(&ri[1], f2o(mx));
+        __syncthreads();
+        lo = o2f(ri[0]);
+        hi = o2f(ri[1]);
+        __syncthreads();
+    }
+    scale = range_scale(d.nb, lo, hi);
+}
+
+// -------------------------------------------------- per-thread membership --
+// For the V last-axis positions a thread owns inside a segment: the first
+// kernel slot hit (or -1), its multiplicity, and any further (slot, mult)
+// pairs packed in 'extra' (at most two more; only near folds of tiny axes).
+template <int V>
+struct Memb {
+    int s1[V];
+    uint32_t w1[V];
+    uint32_t extra[V];
+};
+
+template <int V>
+__device__ __forceinline__ void build_memb(const McVol &d, int kA, int kB, int xs, int xe,
+                                           int x0, Memb<V> &m)
+{
+    const McAxis &a = d.ax[d.D - 1];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int x = x0 + e;
+        m.s1[e] = -1;
+        m.w1[e] = 0;
+        m.extra[e] = 0;
+        if (x < xs || x >= xe) continue;
+        int found = 0;
+        for (int k = kA; k < kB; ++k) {
+            const int w = mc_mult(mc_kernel_box(a, k), x);
+            if (!w) continue;
+            if (found == 0) {
+                m.s1[e] = k - kA;
+                m.w1[e] = (uint32_t)w;
+            } else {
+                m.extra[e] |= ((uint32_t)(k - kA + 1) | ((uint32_t)w << 8)) << (16 * (found - 1));
+            }
+            ++found;
+        }
+    }
+}
+
+// --------------------------------------------------- histogram / AHR range --
+// LDS layout of a histogram unit.
+struct HistLds {
+    HistOTab *otab;     // [MC_OMAX]
+    float *slot_lo;     // [hG]  (AHR)
+    float *slot_sc;     // [hG]  (AHR)
+    int *slot_mm;       // [hG][2] ordered min/max (AHR range pass)
+    uint32_t *h;        // [hG][nb][R]
+    float *red;         // [2*MC_T]
+};
+
+__device__ __forceinline__ HistLds hist_lds(const McVol &d, char *smem)
+{
+    HistLds L;
+    char *p = smem;
+    L.otab = (HistOTab *)p;
+    p += sizeof(HistOTab) * MC_OMAX;
+    L.red = (float *)p;
+    p += sizeof(float) * 2 * MC_T;
+    L.slot_lo = (float *)p;
+    p += sizeof(float) * 64;
+    L.slot_sc = (float *)p;
+    p += sizeof(float) * 64;
+    L.slot_mm = (int *)p;
+    p += sizeof(int) * 128;
+    L.h = (uint32_t *)p;
+    return L;
+}
+
+// Wavefront-aggregated LDS histogram update: lanes whose key equals the
+// first active lane's key add their summed weight with one atomic.
+template <int PEEL>
+__device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int R, int cp)
+{
+    if constexpr (PEEL > 0) {
+        unsigned long long act = __ballot(key >= 0);
+#pragma unroll
+        for (int r = 0; r < PEEL; ++r) {
+            if (!act) break;
+            const int leader = __ffsll((long long)act) - 1;
+            const int lkey = __shfl(key, leader);
+            const bool same = (key == lkey);
+            const unsigned long long sm = __ballot(same);
+            const uint32_t lval = __shfl(val, leader);
+            uint32_t sum;
+            if (__ballot(same && val != lval) == 0ull) {
+                sum = (uint32_t)__popcll(sm) * lval;
+            } else {
+                // weights are products of per-axis multiplicities (< 2^9):
+                // add them bit plane by bit plane with ballots, which only
+                // count active lanes
+                sum = 0;
+#pragma unroll
+                for (int b = 0; b < 9; ++b)
+                    sum += (uint32_t)__popcll(__ballot(same && ((val >> b) & 1u))) << b;
+            }
+            if (lane_id() == leader) atomicAdd(&h[lkey * R + cp], sum);
+            if (same) key = -1;
+            act &= ~sm;
+        }
+    }
+    if (key >= 0) atomicAdd(&h[key * R + cp], val);
+}
+
+template <typename Tin, int V, bool AHR, bool RANGE_ONLY, int PEEL>
+__device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
+{
+    const int D = d.D, nb = d.nb;
+    HistLds L = hist_lds(d, smem);
+    int64_t col;
+    int seg, chunk;
+    RowSpace rs;
+    McBox obox[MC_MAXD], ib;
+    hist_unit(d, wu, col, seg, chunk, rs, obox, ib);
+    int kA, kB, xs, xe;
+    hist_segment(d, seg, kA, kB, xs, xe);
+    const int nslot = kB - kA;
+    const int R = RANGE_ONLY ? 1 : d.hR;
+
+    // rows of this chunk
+    const int64_t r0 = rs.rows * chunk / d.hCr, r1 = rs.rows * (chunk + 1) / d.hCr;
+    const int64_t o0 = r0 / rs.in_len;
+    const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
+    build_hist_otab(d, rs, obox, o0, ocnt, L.otab);
+
+    // global range (GHR) or this unit's kernels' ranges (AHR)
+    float glo = 0.f, gsc = 0.f;
+    const float nbf = (float)nb;
+    const int nbm1 = nb - 1;
+    if constexpr (!RANGE_ONLY) {
+        if constexpr (!AHR) {
+            float ghi;
+            ghr_range(d, L.red, glo, ghi, gsc);
+            if (wu == 0 && threadIdx.x == 0) {
+                d.range[0] = glo;
+                d.range[1] = ghi;
+                d.scale[0] = gsc;
+            }
+        } else {
+            // kernel k's range: reduce the adaptive-range partials of every
+            // unit covering k (all chunks; all parts when a kernel is split)
+            const int64_t cb = col * d.hS;
+            for (int s = threadIdx.x; s < nslot; s += MC_T) {
+                const int k = kA + s;
+                int sg0, nsg, sl;
+                if (d.hP == 1) { sg0 = seg; nsg = 1; sl = s; }
+                else { sg0 = k * d.hP; nsg = d.hP; sl = 0; }
+                float mn = INFINITY, mx = -INFINITY;
+                for (int g = 0; g < nsg; ++g)
+                    for (int c = 0; c < d.hCr; ++c) {
+                        const int64_t u = (cb + sg0 + g) * d.hCr + c;
+                        mn = fminf(mn, d.rpart[(u * d.hG + sl) * 2]);
+                        mx = fmaxf(mx, d.rpart[(u * d.hG + sl) * 2 + 1]);
+                    }
+                L.slot_lo[s] = mn;
+                L.slot_sc[s] = range_scale(nb, mn, mx);
+                if (chunk == 0 && (d.hP == 1 || seg % d.hP == 0)) {
+                    const int64_t kk = col * d.ax[D - 1].n + k;
+                    d.range[2 * kk] = mn;
+                    d.range[2 * kk + 1] = mx;
+                    d.scale[kk] = L.slot_sc[s];
+                }
+            }
+        }
+        const int hsz = nslot * nb * R;
+        for (int i = threadIdx.x; i < hsz; i += MC_T) L.h[i] = 0;
+    } else {
+        for (int i = threadIdx.x; i < 2 * nslot; i += MC_T)
+            L.slot_mm[i] = (i & 1) ? f2o(-INFINITY) : f2o(INFINITY);
+    }
+    __syncthreads();
+
+    // thread -> (chunk of the row segment, row within an iteration); a
+    // split segment may be empty, then the unit only writes zero partials
+    const int c_lo = xs / V, c_hi = xe > xs ? (xe + V - 1) / V : c_lo;
+    const int cpr = c_hi - c_lo;
+    const int rpi = cpr > 0 ? MC_T / cpr : 1;
+    const int tch = cpr > 0 ? (int)threadIdx.x % cpr : 0;
+    const int trow = cpr > 0 ? (int)threadIdx.x / cpr : MC_T;
+    const bool tact = trow < rpi && r0 + trow < r1;
+    Memb<V> m;
+    build_memb<V>(d, kA, kB, xs, xe, (c_lo + tch) * V, m);
+    float lo1[V], sc1[V], mn[V], mx[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        lo1[e] = glo;
+        sc1[e] = gsc;
+        if constexpr (AHR && !RANGE_ONLY) {
+            if (m.s1[e] >= 0) {
+                lo1[e] = L.slot_lo[m.s1[e]];
+                sc1[e] = L.slot_sc[m.s1[e]];
+            }
+        }
+        mn[e] = INFINITY;
+        mx[e] = -INFINITY;
+    }
+    const int cp = R > 1 ? (lane_id() & (R - 1)) : 0;
+    const Tin *in = (const Tin *)d.in;
+
+    if (tact) {
+        const int64_t rstart = r0 + trow;
+        int64_t o = rstart / rs.in_len;
+        int r = (int)(rstart - o * rs.in_len);
+        const int64_t so = rpi / rs.in_len;
+        const int sr = (int)(rpi - so * rs.in_len);
+        const int64_t xoff = (int64_t)(c_lo + tch) * V;
+        for (int64_t row = rstart; row < r1; row += rpi) {
+            const HistOTab te = L.otab[o - o0];
+            const int xin = rs.in_lo + r;
+            const int64_t off = te.off + (int64_t)xin * rs.in_stride + xoff;
+            float f[V];
+            load_chunk<Tin, V>(in + off, f);
+            const uint32_t wrow = te.w * (uint32_t)mc_mult(ib, xin);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if constexpr (RANGE_ONLY) {
+                    mn[e] = fminf(mn[e], f[e]);
+                    mx[e] = fmaxf(mx[e], f[e]);
+                    if (m.extra[e]) {
+                        uint32_t ex = m.extra[e];
+                        while (ex) {
+                            const int s = (int)(ex & 0xff) - 1;
+                            atomicMin(&L.slot_mm[2 * s], f2o(f[e]));
+                            atomicMax(&L.slot_mm[2 * s + 1], f2o(f[e]));
+                            ex >>= 16;
+                        }
+                    }
+                } else {
+                    int key = -1;
+                    if (m.s1[e] >= 0)
+                        key = m.s1[e] * nb + bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
+                    hist_add<PEEL>(L.h, key, wrow * m.w1[e], R, cp);
+                    if (m.extra[e]) {
+                        uint32_t ex = m.extra[e];
+                        while (ex) {
+                            const int s = (int)(ex & 0xff) - 1;
+                            const uint32_t w = (ex >> 8) & 0xff;
+                            const float lo = AHR ? L.slot_lo[s] : glo;
+                            const float sc = AHR ? L.slot_sc[s] : gsc;
+                            atomicAdd(&L.h[(s * nb + bin_of(f[e], lo, sc, nbf, nbm1)) * R + cp],
+                                      wrow * w);
+                            ex >>= 16;
+                        }
+                    }
+                }
+            }
+            r += sr;
+            o += so;
+            if (r >= rs.in_len) {
+                r -= rs.in_len;
+                o += 1;
+            }
+        }
+    }
+    if constexpr (RANGE_ONLY) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            if (m.s1[e] >= 0 && mn[e] <= mx[e]) {
+                atomicMin(&L.slot_mm[2 * m.s1[e]], f2o(mn[e]));
+                atomicMax(&L.slot_mm[2 * m.s1[e] + 1], f2o(mx[e]));
+            }
+        }
+    }
+    __syncthreads();
+    if constexpr (RANGE_ONLY) {
+        for (int s = threadIdx.x; s < d.hG; s += MC_T) {
+            float a = INFINITY, b = -INFINITY;
+            if (s < nslot) {
+                a = o2f(L.slot_mm[2 * s]);
+                b = o2f(L.slot_mm[2 * s + 1]);
+            }
+            d.rpart[((int64_t)wu * d.hG + s) * 2] = a;
+            d.rpart[((int64_t)wu * d.hG + s) * 2 + 1] = b;
+        }
+    } else {
+        // flush: partial histogram of every slot (replicas summed)
+        uint32_t *dst = d.part + (int64_t)wu * d.hG * nb;
+        const int tot = d.hG * nb;
+        for (int i = threadIdx.x; i < tot; i += MC_T) {
+            uint32_t s = 0;
+            if (i < nslot * nb)
+                for (int c = 0; c < R; ++c) s += L.h[i * R + c];
+            dst[i] = s;
+        }
+    }
+}
+
+template <typename Tin, bool AHR, bool RANGE_ONLY, int PEEL>
+__device__ void hist_unit_dispatch(const McVol &d, uint32_t wu, char *smem)
+{
+    constexpr int VM = 16 / sizeof(Tin);
+    if (d.vec == VM) hist_unit_v<Tin, VM, AHR, RANGE_ONLY, PEEL>(d, wu, smem);
+    else hist_unit_v<Tin, 1, AHR, RANGE_ONLY, PEEL>(d, wu, smem);
+}
+
+// ----------------------------------------------------- clip + CDF + LUT --
+// One unit per kernel: sum the partial histograms, clip at C and share the
+// excess equally (H = n*min(h,C) + E, exact), inclusive CDF, normalised LUT.
+__device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
+{
+    unsigned long long *s64 = (unsigned long long *)smem;
+    const int nb = d.nb;
+    const int nl = d.ax[d.D - 1].n;
+    const int64_t col = (int64_t)k / nl;
+    const int kl = (int)(k - col * nl);
+    int sg0, nsg, sl;
+    if (d.hP == 1) { sg0 = kl / d.hG; nsg = 1; sl = kl - sg0 * d.hG; }
+    else { sg0 = kl * d.hP; nsg = d.hP; sl = 0; }
+    const int per = (nb + MC_T - 1) / MC_T;
+    const int j0 = mc_min(nb, (int)threadIdx.x * per), j1 = mc_min(nb, j0 + per);
+    const unsigned long long C = (unsigned long long)d.clipC;
+    uint32_t *hk = d.hist + (int64_t)k * nb;
+    unsigned long long smin = 0, exc = 0;
+    for (int j = j0; j < j1; ++j) {
+        uint32_t h = 0;
+        for (int g = 0; g < nsg; ++g)
+            for (int c = 0; c < d.hCr; ++c) {
+                const int64_t u = (col * d.hS + sg0 + g) * d.hCr + c;
+                h += d.part[(u * d.hG + sl) * nb + j];
+            }
+        hk[j] = h;
+        smin += h < C ? h : C;
+        exc += h > C ? h - C : 0ull;
+    }
+    const unsigned long long E = block_sum_u64(exc, s64);
+    const unsigned long long nbu = (unsigned long long)nb;
+    const unsigned long long tsum = nbu * smin + (unsigned long long)(j1 - j0) * E;
+    const unsigned long long pre = block_exscan_u64(tsum, s64);
+    // c0 = H_0, total = sum H (= n*K); both block-uniform
+    if (threadIdx.x == MC_T - 1) s64[0] = pre + tsum;
+    if (threadIdx.x == 0) {
+        const uint32_t h0 = hk[0];
+        s64[1] = nbu * (h0 < C ? h0 : C) + E;
+    }
+    __syncthreads();
+    const unsigned long long total = s64[0], c0 = s64[1];
+    const unsigned long long den = total - c0;
+    unsigned long long acc = pre;
+    unsigned long long *Hk = d.clipped + (int64_t)k * nb;
+    float *lk = d.lut + (int64_t)k * nb;
+    for (int j = j0; j < j1; ++j) {
+        const uint32_t h = hk[j];
+        const unsigned long long H = nbu * (h < C ? h : C) + E;
+        acc += H;
+        Hk[j] = H;
+        const double m = den == 0 ? (double)j / (double)(nb - 1)
+                                  : (double)(acc - c0) / (double)den;
+        lk[j] = (float)m;
+    }
+}
+
+// ------------------------------------------------------------------- map --
+// Interpolation units: a cell column (one cell per outer axis) x a group of
+// cells on the last axis x a chunk of rows.  The LUTs of the 2^(D-1) outer
+// corner kernels times the group's last-axis kernels are staged in LDS.
+__device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int &chunk, int &grp,
+                                                int32_t (&cidx)[MC_MAXD], RowSpace &rs)
+{
+    const int D = d.D;
+    chunk = (int)(wu % (uint32_t)d.mCr);
+    const uint32_t t1 = wu / (uint32_t)d.mCr;
+    grp = (int)(t1 % (uint32_t)d.mS);
+    int64_t c = (int64_t)(t1 / (uint32_t)d.mS);
+#pragma unroll
+    for (int i = MC_MAXD - 2; i >= 0; --i) {
+        if (i <= D - 2) {
+            const int nc = d.ax[i].n - 1;
+            const int64_t q = c / nc;
+            cidx[i] = (int)(c - q * nc);
+            c = q;
+            int lo, hi;
+            mc_cell_range(d.ax[i], cidx[i], lo, hi);
+            rs.lo[i] = lo;
+            rs.len[i] = hi - lo;
+        }
+    }
+    rowspace_finish(d, rs);
+}
+
+// Weight of x towards the upper kernel of its cell c along axis a.
+__device__ __forceinline__ float cell_weight(const McAxis &a, int c, int x)
+{
+    return __fdiv_rn((float)mc_cell_m(a, c, x), (float)(2 * a.b));
+}
+
+template <int D>
+struct MapOTab {
+    static constexpr int NOH = D >= 3 ? (1 << (D - 2)) : 1;
+    int64_t off;
+    float coef[NOH];
+};
+
+template <typename Tin, int D, bool AHR, int V>
+__device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
+{
+    constexpr int NC = 1 << D;                 // corners
+    constexpr int NO = 1 << (D - 1);           // outer corners
+    using OT = MapOTab<D>;
+    constexpr int NOH = OT::NOH;
+    const int nb = d.nb;
+    int chunk, grp;
+    int32_t cidx[MC_MAXD];
+    RowSpace rs;
+    map_unit_decode(d, wu, chunk, grp, cidx, rs);
+    const McAxis &al = d.ax[D - 1];
+    int cA, cB, xs, xe, tmp;
+    if (d.mP == 1) {
+        cA = grp * d.mG;
+        cB = mc_min(cA + d.mG, al.n - 1);
+        mc_cell_range(al, cA, xs, tmp);
+        mc_cell_range(al, cB - 1, tmp, xe);
+    } else {   // part (grp % mP) of cell (grp / mP)
+        cA = grp / d.mP;
+        cB = cA + 1;
+        const int pp = grp - cA * d.mP;
+        int lo, hi;
+        mc_cell_range(al, cA, lo, hi);
+        xs = lo + (int)((int64_t)(hi - lo) * pp / d.mP);
+        xe = lo + (int)((int64_t)(hi - lo) * (pp + 1) / d.mP);
+    }
+    const int ncl = cB - cA;
+
+    OT *otab = (OT *)smem;
+    float *lut = (float *)(smem + sizeof(OT) * MC_OMAX);
+
+    // kernel-grid strides (last axis fastest)
+    int64_t kst[MC_MAXD];
+    {
+        int64_t s = 1;
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) {
+            kst[i] = s;
+            s *= d.ax[i].n;
+        }
+    }
+    int64_t kbase = 0;   // kernel index of outer corner 0, last-axis kernel 0
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) kbase += (int64_t)cidx[i] * kst[i];
+
+    // stage LUTs: GHR [bin][lk][corner'], AHR [lk*NO + corner'][bin]
+    const int nlk = ncl + 1;
+    const int tot = nb * nlk * NO;
+    for (int i = threadIdx.x; i < tot; i += MC_T) {
+        const int b = i % nb;
+        const int t = i / nb;
+        const int co = t % NO, lk = t / NO;
+        int64_t kid = kbase + cA + lk;
+#pragma unroll
+        for (int j = 0; j < D - 1; ++j)
+            if ((co >> (D - 2 - j)) & 1) kid += kst[j];
+        const float v = d.lut[kid * nb + b];
+        if constexpr (AHR) lut[i] = v;
+        else lut[(b * nlk + lk) * NO + co] = v;
+    }
+    // per-corner ranges (AHR: one last-axis cell per unit)
+    float clo[NC], csc[NC];
+    float glo = 0.f, gsc = 0.f;
+    if constexpr (AHR) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int lk = c / NO, co = c % NO;
+            int64_t kid = kbase + cA + lk;
+#pragma unroll
+            for (int j = 0; j < D - 1; ++j)
+                if ((co >> (D - 2 - j)) & 1) kid += kst[j];
+            clo[c] = d.range[2 * kid];
+            csc[c] = d.scale[kid];
+        }
+    } else {
+        glo = d.range[0];
+        gsc = d.scale[0];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) clo[c] = csc[c] = 0.f;
+    }
+
+    // rows of this chunk and the outer-row table (offsets, partial weights)
+    const int64_t r0 = rs.rows * chunk / d.mCr, r1 = rs.rows * (chunk + 1) / d.mCr;
+    const int64_t o0 = r0 / rs.in_len;
+    const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
+    for (int j = threadIdx.x; j < ocnt; j += MC_T) {
+        int32_t x[MC_MAXD];
+        decode_outer(d, rs, o0 + j, x);
+        int64_t off = 0;
+        float cf[NOH];
+        cf[0] = 1.0f;
+        int n = 1;
+#pragma unroll
+        for (int i = 0; i < D - 2; ++i) {
+            off += (int64_t)x[i] * d.stride[i];
+            const float w = cell_weight(d.ax[i], cidx[i], x[i]);
+            const float omw = 1.0f - w;
+            // tensor product, axis i becomes the next lower-order bit
+#pragma unroll
+            for (int q = NOH - 1; q >= 0; --q) {
+                if (q < 2 * n) {
+                    const float base = cf[q >> 1];
+                    cf[q] = (q & 1) ? base * w : base * omw;
+                }
+            }
+            n *= 2;
+        }
+        otab[j].off = off;
+#pragma unroll
+        for (int q = 0; q < NOH; ++q) otab[j].coef[q] = cf[q];
+    }
+    __syncthreads();
+
+    // thread mapping along the last axis (a split cell part may be empty)
+    if (xe <= xs) return;
+    const int c_lo = xs / V, c_hi = (xe + V - 1) / V;
+    const int cpr = c_hi - c_lo;
+    const int rpi = MC_T / cpr;
+    const int tch = threadIdx.x % cpr, trow = threadIdx.x / cpr;
+    if (!(trow < rpi)) return;
+    const int64_t xoff = (int64_t)(c_lo + tch) * V;
+    int cl[V];
+    float wl[V];
+    bool val[V];
+    bool allv = true;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int x = (int)xoff + e;
+        val[e] = x >= xs && x < xe;
+        allv = allv && val[e];
+        int c = cA;
+        if (val[e]) {
+            // cell of x on the last axis: m = 2(x+p0) - (b-1), c = m / 2b
+            const int m = 2 * (x + al.p0) - (al.b - 1);
+            c = m / (2 * al.b);
+        }
+        cl[e] = c - cA;
+        wl[e] = val[e] ? cell_weight(al, c, x) : 0.f;
+    }
+    const Tin *in = (const Tin *)d.in;
+    const float nbf = (float)nb;
+    const int nbm1 = nb - 1;
+    const int64_t rstart = r0 + trow;
+    int64_t o = rstart / rs.in_len;
+    int r = (int)(rstart - o * rs.in_len);
+    const int64_t so = rpi / rs.in_len;
+    const int sr = (int)(rpi - so * rs.in_len);
+    const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
+    for (int64_t row = rstart; row < r1; row += rpi) {
+        const OT &te = otab[o - o0];
+        const int xin = rs.in_lo + r;
+        const int64_t off = te.off + (int64_t)xin * rs.in_stride + xoff;
+        float f[V];
+        load_chunk<Tin, V>(in + off, f);
+        float rc[NO];
+        if constexpr (D == 1) {
+            rc[0] = 1.0f;
+        } else {
+            const float w = cell_weight(d.ax[D - 2], cidx[D - 2], xin);
+            const float omw = 1.0f - w;
+#pragma unroll
+            for (int q = 0; q < NOH; ++q) {
+                const float cq = D >= 3 ? te.coef[q] : 1.0f;
+                rc[2 * q] = cq * omw;
+                rc[2 * q + 1] = cq * w;
+            }
+        }
+        float y[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float Lv[NC];
+            if constexpr (AHR) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    Lv[c] = lut[c * nb + bin_of(f[e], clo[c], csc[c], nbf, nbm1)];
+            } else {
+                const int b = bin_of(f[e], glo, gsc, nbf, nbm1);
+                const float *p = lut + (b * nlk + cl[e]) * NO;
+                if constexpr (NO % 4 == 0) {
+#pragma unroll
+                    for (int c = 0; c < NC; c += 4) {
+                        const float4 q = *reinterpret_cast<const float4 *>(p + c);
+                        Lv[c] = q.x;
+                        Lv[c + 1] = q.y;
+                        Lv[c + 2] = q.z;
+                        Lv[c + 3] = q.w;
+                    }
+                } else if constexpr (NO % 2 == 0) {
+#pragma unroll
+                    for (int c = 0; c < NC; c += 2) {
+                        const float2 q = *reinterpret_cast<const float2 *>(p + c);
+                        Lv[c] = q.x;
+                        Lv[c + 1] = q.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) Lv[c] = p[c];
+                }
+            }
+            float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
+#pragma unroll
+            for (int c = 1; c < NO; ++c) {
+                A = __fmaf_rn(rc[c], Lv[c], A);
+                B = __fmaf_rn(rc[c], Lv[NO + c], B);
+            }
+            y[e] = __fmaf_rn(wl[e], B - A, A);
+        }
+        if (vecst) {
+            if constexpr (V % 4 == 0) {
+                f4 *op = (f4 *)((float *)d.out + off);
+#pragma unroll
+                for (int q = 0; q < V / 4; ++q) {
+                    f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                    __builtin_nontemporal_store(t, op + q);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
+        }
+        r += sr;
+        o += so;
+        if (r >= rs.in_len) {
+            r -= rs.in_len;
+            o += 1;
+        }
+    }
+}
+
+template <typename Tin, int D, bool AHR>
+__device__ void map_unit(const McVol &d, uint32_t wu, char *smem)
+{
+    constexpr int VM = 16 / sizeof(Tin);
+    if (d.vec == VM) map_unit_v<Tin, D, AHR, VM>(d, wu, smem);
+    else map_unit_v<Tin, D, AHR, 1>(d, wu, smem);
+}
+
+// Generic interpolation (any D up to 8, or LUTs too large for LDS): one cell
+// per unit, LUTs read from global memory, corners summed in index order.
+template <typename Tin, bool AHR>
+__device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
+{
+    const int D = d.D, nb = d.nb;
+    const int NC = 1 << D;
+    int chunk, grp;
+    int32_t cidx[MC_MAXD];
+    RowSpace rs;
+    map_unit_decode(d, wu, chunk, grp, cidx, rs);
+    const McAxis &al = d.ax[D - 1];
+    const int cl = grp;   // one cell per unit on the last axis (mG == 1)
+    int xs, xe;
+    mc_cell_range(al, cl, xs, xe);
+    int64_t kst[MC_MAXD];
+    int64_t kbase = 0;
+    {
+        int64_t s = 1;
+#pragma unroll
+        for (int i = MC_MAXD - 1; i >= 0; --i) {
+            if (i <= D - 1) {
+                kst[i] = s;
+                s *= d.ax[i].n;
+            } else {
+                kst[i] = 0;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) {
+        if (i <= D - 2) kbase += (int64_t)cidx[i] * kst[i];
+        if (i == D - 1) kbase += (int64_t)cl * kst[i];
+    }
+    float glo = 0.f, gsc = 0.f;
+    if (!AHR) {
+        glo = d.range[0];
+        gsc = d.scale[0];
+    }
+    const int64_t r0 = rs.rows * chunk / d.mCr, r1 = rs.rows * (chunk + 1) / d.mCr;
+    const int xl = xe - xs;
+    const int64_t nel = (r1 - r0) * xl;
+    const float nbf = (float)nb;
+    const int nbm1 = nb - 1;
+    for (int64_t e = threadIdx.x; e < nel; e += MC_T) {
+        const int64_t row = r0 + e / xl;
+        const int x = xs + (int)(e - (row - r0) * xl);
+        // decode the row into outer coordinates
+        int32_t xc[MC_MAXD];
+        int64_t rr = row;
+        int64_t off = x;
+#pragma unroll
+        for (int i = MC_MAXD - 2; i >= 0; --i) {
+            if (i <= D - 2) {
+                const int64_t q = rr / rs.len[i];
+                xc[i] = rs.lo[i] + (int)(rr - q * rs.len[i]);
+                rr = q;
+                off += (int64_t)xc[i] * d.stride[i];
+            }
+        }
+        float w[MC_MAXD];
+#pragma unroll
+        for (int i = 0; i < MC_MAXD; ++i) {
+            if (i <= D - 2) w[i] = cell_weight(d.ax[i], cidx[i], xc[i]);
+            if (i == D - 1) w[i] = cell_weight(al, cl, x);
+        }
+        const float v = load_elem(d.in, d.in_dt, off);
+        float y = 0.0f;
+        for (int c = 0; c < NC; ++c) {
+            float coef = 1.0f;
+            int64_t kid = kbase;
+#pragma unroll
+            for (int i = 0; i < MC_MAXD; ++i) {
+                if (i <= D - 1) {
+                    const int bit = (c >> (D - 1 - i)) & 1;
+                    coef *= bit ? w[i] : 1.0f - w[i];
+                    kid += bit ? kst[i] : 0;
+                }
+            }
+            const float lo = AHR ? d.range[2 * kid] : glo;
+            const float sc = AHR ? d.scale[kid] : gsc;
+            y = __fmaf_rn(coef, d.lut[kid * nb + bin_of(v, lo, sc, nbf, nbm1)], y);
+        }
+        store_elem(d.out, d.out_dt, off, y);
+    }
+}
+
+}  // namespace mc

@@ -1,0 +1,1031 @@
+// Host runtime and C ABI of the MI355X MCLAHE library (see include/mclahe.h).
+//
+// mclahe_run        : four stream-ordered launches (range, histogram,
+//                     clip/CDF/LUT, interpolation), one work-group per unit.
+// mclahe_run_batched: one persistent kernel that pulls the units of many
+//                     volumes from a phase-ordered ticket queue, replayed from
+//                     a cached hipGraph (descriptor copy, counter reset,
+//                     persistent launch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mclahe.h"
+#include "mc_desc.h"
+#include "mc_kernels.h"
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string g_err;
+
+static mclahe_status fail(mclahe_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(MCLAHE_ERROR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------- plan --
+struct mclahe_plan_s {
+    int D;
+    int64_t shape[MC_MAXD], ks[MC_MAXD];
+    int nb;
+    float clip;
+    int mode;
+    int has_ur;
+    float ur[2];
+    int in_dt, out_dt;
+    McAxis ax[MC_MAXD];
+    int64_t stride[MC_MAXD];
+    int64_t nvox, nker, K, clipC, ncells;
+    mclahe_tuning tune;  // requested (0 = default)
+    McVol v;             // derived descriptor (no pointers)
+    // workspace layout
+    uint64_t o_part, o_rpart, o_hist, o_clipped, o_lut, o_range, o_scale, total;
+    size_t lds_range, lds_hist, lds_clip, lds_map;
+};
+
+static size_t esize(int dt) { return dt == MC_U8 ? 1 : dt == MC_U16 ? 2 : 4; }
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Header bytes of a histogram unit's LDS (see mc::hist_lds).
+static size_t hist_lds_header() { return sizeof(mc::HistOTab) * MC_OMAX + 4 * 2 * MC_T + 4 * 64 * 2 + 4 * 128; }
+
+static size_t map_otab_bytes(int D)
+{
+    switch (D) {
+    case 1: return sizeof(mc::MapOTab<1>) * MC_OMAX;
+    case 2: return sizeof(mc::MapOTab<2>) * MC_OMAX;
+    case 3: return sizeof(mc::MapOTab<3>) * MC_OMAX;
+    default: return sizeof(mc::MapOTab<4>) * MC_OMAX;
+    }
+}
+
+static size_t map_lut_bytes(const mclahe_plan_s *p, int mG)
+{
+    const int D = p->D;
+    if (p->mode == MC_AHR) return (size_t)(1 << D) * p->nb * 4;
+    return (size_t)p->nb * (mG + 1) * (1 << (D - 1)) * 4;
+}
+
+// Extent of the last-axis hist segment made of kernels [kA,kB).
+static void seg_extent(const McAxis &a, int kA, int kB, int &xs, int &xe)
+{
+    xs = INT32_MAX;
+    xe = -1;
+    for (int k = kA; k < kB; ++k) {
+        McBox b = mc_kernel_box(a, k);
+        xs = std::min(xs, b.lo);
+        xe = std::max(xe, b.hi);
+    }
+}
+
+// Chunks of V elements a segment [xs, xe) spans.
+static int seg_chunks(int xs, int xe, int V) { return (xe + V - 1) / V - xs / V; }
+
+// Derive the work decomposition and workspace layout from the tuning.
+static mclahe_status derive(mclahe_plan_s *p)
+{
+    McVol &v = p->v;
+    memset(&v, 0, sizeof v);
+    const int D = p->D;
+    v.D = D;
+    v.nb = p->nb;
+    v.in_dt = p->in_dt;
+    v.out_dt = p->out_dt;
+    v.mode = p->mode;
+    v.has_user_range = p->has_ur;
+    v.user_lo = p->ur[0];
+    v.user_hi = p->ur[1];
+    v.clipC = p->clipC;
+    v.K = p->K;
+    for (int i = 0; i < MC_MAXD; ++i) {
+        v.ax[i] = p->ax[i];
+        v.stride[i] = p->stride[i];
+    }
+    v.nvox = p->nvox;
+    v.nker = p->nker;
+    const McAxis &al = p->ax[D - 1];
+    const int vmax = 16 / (int)esize(p->in_dt);
+    const int V = (al.s % vmax == 0) ? vmax : 1;
+    v.vec = V;
+    const int maxchunks = MC_T - 1;
+    const mclahe_tuning &t = p->tune;
+
+    // ---- histogram units --------------------------------------------------
+    int R = t.hist_copies > 0 ? t.hist_copies : 2;
+    if (R != 1 && R != 2 && R != 4 && R != 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "hist_copies must be 1, 2, 4 or 8");
+    const size_t hdr = hist_lds_header();
+    while (R > 1 && hdr + (size_t)p->nb * R * 4 > MC_LDS_BUDGET) R /= 2;
+    if (hdr + (size_t)p->nb * 4 > MC_LDS_BUDGET)
+        return fail(MCLAHE_ERROR_NOT_SUPPORTED, "n_bins=%d needs more LDS than a work-group may use", p->nb);
+    int Gmax = (int)std::min<size_t>(64, (MC_LDS_BUDGET - hdr) / ((size_t)p->nb * R * 4));
+    Gmax = std::max(1, std::min(Gmax, al.n));
+    int G = 0;
+    for (int g = Gmax; g >= 1; --g) {
+        bool ok = true;
+        for (int kA = 0; kA < al.n && ok; kA += g) {
+            int xs, xe;
+            seg_extent(al, kA, std::min(kA + g, al.n), xs, xe);
+            ok = seg_chunks(xs, xe, V) <= maxchunks;
+        }
+        if (ok) {
+            G = g;
+            break;
+        }
+    }
+    int P = 1;
+    if (G == 0) {   // one kernel is too long for a work-group row: split it
+        G = 1;
+        int maxlen = 0;
+        for (int k = 0; k < al.n; ++k) {
+            McBox b = mc_kernel_box(al, k);
+            maxlen = std::max(maxlen, b.hi - b.lo);
+        }
+        P = 2;
+        for (;; ++P) {
+            bool ok = true;
+            for (int k = 0; k < al.n && ok; ++k) {
+                McBox b = mc_kernel_box(al, k);
+                const int len = b.hi - b.lo;
+                for (int pp = 0; pp < P && ok; ++pp) {
+                    const int xs = b.lo + (int)((int64_t)len * pp / P);
+                    const int xe = b.lo + (int)((int64_t)len * (pp + 1) / P);
+                    ok = seg_chunks(xs, xe, V) <= maxchunks;
+                }
+            }
+            if (ok) break;
+        }
+    }
+    v.hG = G;
+    v.hP = P;
+    v.hS = P == 1 ? (al.n + G - 1) / G : al.n * P;
+    v.hR = R;
+    // hist_peel: 0 = default (one round), k >= 1 = k - 1 rounds
+    v.hPeel = t.hist_peel > 0 ? std::min(t.hist_peel - 1, 2) : 1;
+    v.hCols = 1;
+    int64_t omax_h = 1, rmax_h = 1;
+    for (int i = 0; i < D - 1; ++i) {
+        v.hCols *= p->ax[i].n;
+        int mx = 0;
+        for (int k = 0; k < p->ax[i].n; ++k) {
+            McBox b = mc_kernel_box(p->ax[i], k);
+            mx = std::max(mx, b.hi - b.lo);
+        }
+        rmax_h *= mx;
+        if (i <= D - 3) omax_h *= mx;
+    }
+    const int64_t crmin_h = std::max<int64_t>(1, (omax_h + MC_OMAX - 5) / (MC_OMAX - 4));
+    int64_t cr = t.hist_rows_split > 0 ? t.hist_rows_split
+                                       : (2048 + v.hCols * v.hS - 1) / (v.hCols * v.hS);
+    cr = std::max<int64_t>(cr, crmin_h);
+    cr = std::min<int64_t>(cr, std::max<int64_t>(rmax_h, crmin_h));
+    if (cr > (1 << 20)) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "row split too large");
+    v.hCr = (int)cr;
+    const int64_t nhu = v.hCols * v.hS * v.hCr;
+    if (nhu >= (int64_t)1 << 31) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "too many histogram units");
+    v.n_hist_wu = (uint32_t)nhu;
+    if (p->mode == MC_GHR) {
+        v.n_range_wu = p->has_ur ? 0 : (uint32_t)std::min<int64_t>(1024, std::max<int64_t>(1, p->nvox / (MC_T * 64)));
+    } else {
+        v.n_range_wu = 0;
+    }
+    v.n_clip_wu = (uint32_t)p->nker;
+
+    // ---- interpolation units ----------------------------------------------
+    const size_t otab = map_otab_bytes(D);
+    const bool fast = D <= 4 && otab + map_lut_bytes(p, 1) <= MC_LDS_BUDGET;
+    v.path = fast ? 0 : 1;
+    const int ncl = al.n - 1;  // cells on the last axis
+    int mG = 1;
+    if (fast && p->mode == MC_GHR) {
+        int want = t.map_group > 0 ? t.map_group : ncl;
+        want = std::min(want, ncl);
+        for (int g = want; g >= 1; --g) {
+            if (otab + map_lut_bytes(p, g) > MC_LDS_BUDGET) continue;
+            bool ok = true;
+            for (int cA = 0; cA < ncl && ok; cA += g) {
+                int xs, xe, tmp;
+                mc_cell_range(al, cA, xs, tmp);
+                mc_cell_range(al, std::min(cA + g, ncl) - 1, tmp, xe);
+                ok = seg_chunks(xs, xe, V) <= maxchunks;
+            }
+            if (ok) {
+                mG = g;
+                break;
+            }
+        }
+    }
+    int mP = 1;
+    if (fast) {   // a cell too long for one work-group row is split in parts
+        for (;; ++mP) {
+            bool ok = true;
+            for (int c = 0; c < ncl && ok; ++c) {
+                int lo, hi;
+                mc_cell_range(al, c, lo, hi);
+                for (int pp = 0; pp < mP && ok; ++pp) {
+                    const int xs = lo + (int)((int64_t)(hi - lo) * pp / mP);
+                    const int xe = lo + (int)((int64_t)(hi - lo) * (pp + 1) / mP);
+                    ok = seg_chunks(xs, xe, V) <= maxchunks;
+                }
+            }
+            if (ok) break;
+        }
+        if (mP > 1) mG = 1;
+    }
+    v.mG = mG;
+    v.mP = mP;
+    v.mS = mP > 1 ? ncl * mP : (ncl + mG - 1) / mG;
+    v.mCols = 1;
+    int64_t omax_m = 1, rmax_m = 1;
+    for (int i = 0; i < D - 1; ++i) {
+        v.mCols *= p->ax[i].n - 1;
+        rmax_m *= p->ax[i].b;
+        if (i <= D - 3) omax_m *= p->ax[i].b;
+    }
+    const int64_t crmin_m = fast ? std::max<int64_t>(1, (omax_m + MC_OMAX - 5) / (MC_OMAX - 4)) : 1;
+    int64_t mcr = t.map_rows_split > 0 ? t.map_rows_split
+                                       : (2048 + v.mCols * v.mS - 1) / (v.mCols * v.mS);
+    mcr = std::max<int64_t>(mcr, crmin_m);
+    mcr = std::min<int64_t>(mcr, std::max<int64_t>(rmax_m, crmin_m));
+    v.mCr = (int)mcr;
+    const int64_t nmu = v.mCols * v.mS * v.mCr;
+    if (nmu >= (int64_t)1 << 31) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "too many map units");
+    v.n_map_wu = (uint32_t)nmu;
+
+    // ---- workspace layout -------------------------------------------------
+    uint64_t o = 0;
+    p->o_part = o;
+    o = align256(o + (uint64_t)v.n_hist_wu * v.hG * v.nb * 4);
+    p->o_rpart = o;
+    const uint64_t nrp = p->mode == MC_GHR ? (uint64_t)std::max<uint32_t>(v.n_range_wu, 1) * 2
+                                           : (uint64_t)v.n_hist_wu * v.hG * 2;
+    o = align256(o + nrp * 4);
+    p->o_hist = o;
+    o = align256(o + (uint64_t)p->nker * p->nb * 4);
+    p->o_clipped = o;
+    o = align256(o + (uint64_t)p->nker * p->nb * 8);
+    p->o_lut = o;
+    o = align256(o + (uint64_t)p->nker * p->nb * 4);
+    p->o_range = o;
+    o = align256(o + (p->mode == MC_AHR ? (uint64_t)p->nker * 2 : 2) * 4);
+    p->o_scale = o;
+    o = align256(o + (p->mode == MC_AHR ? (uint64_t)p->nker : 1) * 4);
+    p->total = o;
+
+    p->lds_range = 2 * MC_T * 4;
+    p->lds_hist = hdr + (size_t)v.hG * v.nb * v.hR * 4;
+    p->lds_clip = MC_T * 8;
+    p->lds_map = fast ? otab + map_lut_bytes(p, v.mG) : 0;
+    return MCLAHE_SUCCESS;
+}
+
+// Pointers of a run's descriptor.
+static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, char *ws)
+{
+    v = p->v;
+    v.in = in;
+    v.out = out;
+    v.part = (uint32_t *)(ws + p->o_part);
+    v.rpart = (float *)(ws + p->o_rpart);
+    v.hist = (uint32_t *)(ws + p->o_hist);
+    v.clipped = (unsigned long long *)(ws + p->o_clipped);
+    v.lut = (float *)(ws + p->o_lut);
+    v.range = (float *)(ws + p->o_range);
+    v.scale = (float *)(ws + p->o_scale);
+    const size_t es_in = esize(p->in_dt);
+    if (v.vec > 1 && (((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0)) v.vec = 1;
+    (void)es_in;
+}
+
+// Kernel selection lives in the per-dtype translation units (k_plain_*.hip)
+// and the persistent kernel in k_persist.hip.
+#include "mc_launch.h"
+
+__global__ __launch_bounds__(MC_T) void k_clip(McVol d)
+{
+    extern __shared__ __align__(16) char smem[];
+    mc::clip_unit(d, blockIdx.x, smem);
+}
+
+static KFn pick_range(int dt)
+{
+    return dt == MC_U8 ? mc_pick_range_u8() : dt == MC_U16 ? mc_pick_range_u16() : mc_pick_range_f32();
+}
+static KFn pick_hist(int dt, bool ahr, bool ro, int peel)
+{
+    return dt == MC_U8 ? mc_pick_hist_u8(ahr, ro, peel)
+         : dt == MC_U16 ? mc_pick_hist_u16(ahr, ro, peel) : mc_pick_hist_f32(ahr, ro, peel);
+}
+static KFn pick_map(int dt, int D, bool ahr, int path)
+{
+    return dt == MC_U8 ? mc_pick_map_u8(D, ahr, path)
+         : dt == MC_U16 ? mc_pick_map_u16(D, ahr, path) : mc_pick_map_f32(D, ahr, path);
+}
+
+static mclahe_status launch(KFn f, uint32_t grid, size_t lds, hipStream_t st, const McVol &v)
+{
+    if (grid == 0) return MCLAHE_SUCCESS;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(MC_T), lds, st, v);
+    HIPCHK(hipGetLastError());
+    return MCLAHE_SUCCESS;
+}
+
+static mclahe_status run_plain(const mclahe_plan_s *p, const McVol &v, hipStream_t st,
+                               hipEvent_t *ev = nullptr)
+{
+    const bool ahr = p->mode == MC_AHR;
+    mclahe_status s;
+    if (ev) HIPCHK(hipEventRecord(ev[0], st));
+    if (!ahr) {
+        if ((s = launch(pick_range(p->in_dt), v.n_range_wu, p->lds_range, st, v))) return s;
+    } else {
+        if ((s = launch(pick_hist(p->in_dt, true, true, 0), v.n_hist_wu, p->lds_hist, st, v)))
+            return s;
+    }
+    if (ev) HIPCHK(hipEventRecord(ev[1], st));
+    if ((s = launch(pick_hist(p->in_dt, ahr, false, v.hPeel), v.n_hist_wu, p->lds_hist, st, v)))
+        return s;
+    if (ev) HIPCHK(hipEventRecord(ev[2], st));
+    if ((s = launch((KFn)k_clip, v.n_clip_wu, p->lds_clip, st, v))) return s;
+    if (ev) HIPCHK(hipEventRecord(ev[3], st));
+    if ((s = launch(pick_map(p->in_dt, p->D, ahr, v.path), v.n_map_wu, p->lds_map, st, v))) return s;
+    if (ev) HIPCHK(hipEventRecord(ev[4], st));
+    return MCLAHE_SUCCESS;
+}
+
+struct mclahe_timer_s {
+    std::vector<hipEvent_t> ev;   // 5 per run
+    int max_runs = 0, runs = 0;
+};
+
+// Batched workspace: [queue header | done counters | batch header | vstart |
+// volume table | per-volume workspaces...]
+struct BatchLayout {
+    uint64_t o_queue, o_done, o_hdr, o_vstart, o_vols, o_first, total;
+    std::vector<uint64_t> vol_off;
+    size_t lds;
+};
+
+static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout &L)
+{
+    if (n < 1 || !plans) return fail(MCLAHE_ERROR_INVALID_VALUE, "batched call needs n >= 1 plans");
+    uint64_t o = 0;
+    L.o_queue = o;
+    o = align256(o + sizeof(McQueue));
+    L.o_done = o;
+    o = align256(o + (uint64_t)MC_PHASES * n * 4);
+    L.o_hdr = o;
+    o = align256(o + sizeof(McBatch));
+    L.o_vstart = o;
+    o = align256(o + (uint64_t)MC_PHASES * (n + 1) * 4);
+    L.o_vols = o;
+    o = align256(o + (uint64_t)n * sizeof(McVol));
+    L.o_first = o;
+    L.vol_off.resize(n);
+    L.lds = 2 * MC_T * 8;
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan %d is NULL", i);
+        L.vol_off[i] = o;
+        o = align256(o + plans[i]->total);
+        const mclahe_plan_s *p = plans[i];
+        L.lds = std::max({L.lds, p->lds_range, p->lds_hist, p->lds_clip, p->lds_map});
+    }
+    L.total = o;
+    return MCLAHE_SUCCESS;
+}
+
+// Host image of the table region [o_hdr, o_first).
+static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins, void *const *outs,
+                       char *ws, const BatchLayout &L, std::vector<char> &img)
+{
+    img.assign(L.o_first - L.o_hdr, 0);
+    McBatch *h = (McBatch *)img.data();
+    uint32_t *vs = (uint32_t *)(img.data() + (L.o_vstart - L.o_hdr));
+    McVol *vols = (McVol *)(img.data() + (L.o_vols - L.o_hdr));
+    for (int i = 0; i < n; ++i) bind(plans[i], vols[i], ins[i], outs[i], ws + L.vol_off[i]);
+    h->nvol = (uint32_t)n;
+    uint32_t acc = 0;
+    for (int ph = 0; ph < MC_PHASES; ++ph) {
+        h->phase_start[ph] = acc;
+        uint32_t in_ph = 0;
+        for (int i = 0; i < n; ++i) {
+            vs[ph * (n + 1) + i] = in_ph;
+            const McVol &v = vols[i];
+            const uint32_t c = ph == 0 ? (v.mode == MC_AHR ? v.n_hist_wu : v.n_range_wu)
+                             : ph == 1 ? v.n_hist_wu : ph == 2 ? v.n_clip_wu : v.n_map_wu;
+            in_ph += c;
+        }
+        vs[ph * (n + 1) + n] = in_ph;
+        acc += in_ph;
+    }
+    h->phase_start[MC_PHASES] = acc;
+    h->total = acc;
+    h->spin_limit = 1u << 24;
+}
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy = nullptr;
+    std::vector<char *> host;     // pinned descriptor images (ring)
+    std::vector<hipEvent_t> ev;   // completion of the launch that used a slot
+    std::vector<bool> used;
+    int next = 0;
+    size_t bytes = 0;
+};
+
+static std::mutex g_graph_mu;
+static std::map<std::string, GraphEntry *> g_graphs;
+
+static int persistent_grid(size_t lds, int want)
+{
+    if (want > 0) return want;
+    int dev = 0, ncu = MC_NUM_CU, occ = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, mc_persistent_fn(), MC_T, lds) != hipSuccess || occ < 1)
+        occ = 1;
+    return ncu * occ;
+}
+
+static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, char *ws, int grid)
+{
+    HIPCHK(hipGraphCreate(&g->graph, 0));
+    // 1. descriptor table copy (host image of the current call)
+    HIPCHK(hipGraphAddMemcpyNode1D(&g->copy, g->graph, nullptr, 0, ws + L.o_hdr, g->host[0], g->bytes,
+                                   hipMemcpyHostToDevice));
+    // 2. reset of the queue head, error word and completion counters
+    hipGraphNode_t zero;
+    hipKernelNodeParams zp = {};
+    uint32_t *zptr = (uint32_t *)(ws + L.o_queue);
+    uint32_t zn = (uint32_t)((L.o_hdr - L.o_queue) / 4);
+    void *zargs[] = {&zptr, &zn};
+    zp.func = (void *)mc_zero_fn();
+    zp.gridDim = dim3(std::max<uint32_t>(1, std::min<uint32_t>(64, (zn + 255) / 256)));
+    zp.blockDim = dim3(256);
+    zp.sharedMemBytes = 0;
+    zp.kernelParams = zargs;
+    HIPCHK(hipGraphAddKernelNode(&zero, g->graph, nullptr, 0, &zp));
+    // 3. the persistent kernel
+    hipGraphNode_t pers;
+    hipKernelNodeParams pp = {};
+    const McBatch *hdr = (const McBatch *)(ws + L.o_hdr);
+    const uint32_t *vstart = (const uint32_t *)(ws + L.o_vstart);
+    const McVol *vols = (const McVol *)(ws + L.o_vols);
+    McQueue *q = (McQueue *)(ws + L.o_queue);
+    uint32_t *done = (uint32_t *)(ws + L.o_done);
+    void *pargs[] = {&hdr, &vstart, &vols, &q, &done};
+    pp.func = (void *)mc_persistent_fn();
+    pp.gridDim = dim3(grid);
+    pp.blockDim = dim3(MC_T);
+    pp.sharedMemBytes = (unsigned)L.lds;
+    pp.kernelParams = pargs;
+    hipGraphNode_t deps[2] = {g->copy, zero};
+    HIPCHK(hipGraphAddKernelNode(&pers, g->graph, deps, 2, &pp));
+    HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    return MCLAHE_SUCCESS;
+}
+
+// --------------------------------------------------------------- autotune --
+static std::mutex g_tune_mu;
+static std::map<std::string, mclahe_tuning> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static std::string plan_key(const mclahe_plan_s *p)
+{
+    std::string k = "D" + std::to_string(p->D);
+    for (int i = 0; i < p->D; ++i) k += "_" + std::to_string(p->shape[i]) + "x" + std::to_string(p->ks[i]);
+    k += "_n" + std::to_string(p->nb) + "_m" + std::to_string(p->mode) + "_i" + std::to_string(p->in_dt) +
+         "_o" + std::to_string(p->out_dt) + "_u" + std::to_string(p->has_ur);
+    return k;
+}
+
+static void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = getenv("MCLAHE_TUNE_CACHE");
+    if (!f) return;
+    FILE *fp = fopen(f, "r");
+    if (!fp) return;
+    char key[512];
+    mclahe_tuning t;
+    while (fscanf(fp, "%511s %d %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
+                  &t.map_rows_split, &t.map_group, &t.persistent_blocks) == 7)
+        g_tune_cache[key] = t;
+    fclose(fp);
+}
+
+static void tune_cache_store(const std::string &key, const mclahe_tuning &t)
+{
+    g_tune_cache[key] = t;
+    const char *f = getenv("MCLAHE_TUNE_CACHE");
+    if (!f) return;
+    FILE *fp = fopen(f, "a");
+    if (!fp) return;
+    fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
+            t.map_rows_split, t.map_group, t.persistent_blocks);
+    fclose(fp);
+}
+
+static std::vector<mclahe_tuning> tune_candidates(const mclahe_plan_s *p)
+{
+    std::vector<mclahe_tuning> c;
+    const McVol &v = p->v;
+    const int hcr = v.hCr, mcr = v.mCr;
+    for (int R : {1, 2, 4})
+        for (int peel : {1, 2, 3})
+            for (int f : {1, 2, 4}) {
+                mclahe_tuning t = {};
+                t.hist_copies = R;
+                t.hist_peel = peel;
+                t.hist_rows_split = std::max(1, hcr * f / 2);
+                t.map_rows_split = mcr;
+                t.map_group = v.mG;
+                c.push_back(t);
+            }
+    return c;
+}
+
+// ---------------------------------------------------------------- C ABI --
+extern "C" {
+
+const char *mclahe_version(void) { return "0.1.0"; }
+
+const char *mclahe_status_string(mclahe_status s)
+{
+    switch (s) {
+    case MCLAHE_SUCCESS: return "MCLAHE_SUCCESS";
+    case MCLAHE_ERROR_INVALID_VALUE: return "MCLAHE_ERROR_INVALID_VALUE";
+    case MCLAHE_ERROR_NOT_SUPPORTED: return "MCLAHE_ERROR_NOT_SUPPORTED";
+    case MCLAHE_ERROR_OUT_OF_MEMORY: return "MCLAHE_ERROR_OUT_OF_MEMORY";
+    case MCLAHE_ERROR_WORKSPACE: return "MCLAHE_ERROR_WORKSPACE";
+    case MCLAHE_ERROR_HIP: return "MCLAHE_ERROR_HIP";
+    }
+    return "MCLAHE_UNKNOWN_STATUS";
+}
+
+const char *mclahe_last_error(void) { return g_err.c_str(); }
+
+mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, const int64_t *kernel_size,
+                          int n_bins, float clip_limit, mclahe_range_mode mode, const float *user_range,
+                          mclahe_dtype in_dtype, mclahe_dtype out_dtype)
+{
+    g_err.clear();
+    if (!plan) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan pointer is NULL");
+    *plan = nullptr;
+    if (ndim < 1 || ndim > MC_MAXD) return fail(MCLAHE_ERROR_INVALID_VALUE, "ndim must be in 1..8 (got %d)", ndim);
+    if (!shape || !kernel_size) return fail(MCLAHE_ERROR_INVALID_VALUE, "shape/kernel_size is NULL");
+    if (n_bins < 2 || n_bins > 8192) return fail(MCLAHE_ERROR_INVALID_VALUE, "n_bins must be in 2..8192 (got %d)", n_bins);
+    if (!(clip_limit >= 0.0f) || std::isinf(clip_limit))
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "clip_limit must be finite and >= 0");
+    if (mode != MCLAHE_RANGE_GLOBAL && mode != MCLAHE_RANGE_KERNEL)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "unknown range mode %d", (int)mode);
+    if (in_dtype < MCLAHE_U8 || in_dtype > MCLAHE_F32 || out_dtype < MCLAHE_U8 || out_dtype > MCLAHE_F32)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "unknown dtype");
+    if (user_range) {
+        if (mode != MCLAHE_RANGE_GLOBAL)
+            return fail(MCLAHE_ERROR_INVALID_VALUE, "a user range is only valid with the global range mode");
+        if (!std::isfinite(user_range[0]) || !std::isfinite(user_range[1]) || !(user_range[0] < user_range[1]))
+            return fail(MCLAHE_ERROR_INVALID_VALUE, "user range must be finite with lo < hi");
+    }
+    mclahe_plan_s *p = new (std::nothrow) mclahe_plan_s();
+    if (!p) return fail(MCLAHE_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    p->D = ndim;
+    p->nb = n_bins;
+    p->clip = clip_limit;
+    p->mode = mode;
+    p->has_ur = user_range != nullptr;
+    p->ur[0] = user_range ? user_range[0] : 0.f;
+    p->ur[1] = user_range ? user_range[1] : 0.f;
+    p->in_dt = in_dtype;
+    p->out_dt = out_dtype;
+    p->nvox = 1;
+    p->nker = 1;
+    p->K = 1;
+    p->ncells = 1;
+    for (int i = 0; i < ndim; ++i) {
+        const int64_t s = shape[i], b = kernel_size[i];
+        if (s < 1 || s > INT32_MAX / 4) {
+            delete p;
+            return fail(MCLAHE_ERROR_INVALID_VALUE, "shape[%d]=%lld out of range", i, (long long)s);
+        }
+        if (b < 1 || b > s) {
+            delete p;
+            return fail(MCLAHE_ERROR_INVALID_VALUE, "kernel_size[%d]=%lld must be in 1..shape[%d]=%lld", i,
+                        (long long)b, i, (long long)s);
+        }
+        p->shape[i] = s;
+        p->ks[i] = b;
+        const int64_t pad = 2 * b - 1 - ((s - 1) % b);   // Eq. 1
+        p->ax[i].s = (int32_t)s;
+        p->ax[i].b = (int32_t)b;
+        p->ax[i].p0 = (int32_t)(pad / 2);                // Eq. 2
+        p->ax[i].p1 = (int32_t)((pad + 1) / 2);
+        p->ax[i].n = (int32_t)((s + pad) / b);
+        p->nvox *= s;
+        p->nker *= p->ax[i].n;
+        p->K *= b;
+        p->ncells *= p->ax[i].n - 1;
+        if (p->nvox >= ((int64_t)1 << 40) || p->nker >= ((int64_t)1 << 31)) {
+            delete p;
+            return fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large");
+        }
+    }
+    for (int i = ndim; i < MC_MAXD; ++i) {
+        p->ax[i] = McAxis{1, 1, 0, 1, 2};
+        p->shape[i] = p->ks[i] = 1;
+    }
+    if (p->K >= ((int64_t)1 << 32)) {
+        delete p;
+        return fail(MCLAHE_ERROR_NOT_SUPPORTED, "kernel voxel count must be < 2^32");
+    }
+    int64_t st = 1;
+    for (int i = ndim - 1; i >= 0; --i) {
+        p->stride[i] = st;
+        st *= p->shape[i];
+    }
+    for (int i = ndim; i < MC_MAXD; ++i) p->stride[i] = 0;
+    p->clipC = (int64_t)std::floor((double)clip_limit * (double)p->K);
+    memset(&p->tune, 0, sizeof p->tune);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto it = g_tune_cache.find(plan_key(p));
+        if (it != g_tune_cache.end()) p->tune = it->second;
+    }
+    mclahe_status s = derive(p);
+    if (s != MCLAHE_SUCCESS && (p->tune.hist_rows_split || p->tune.map_rows_split)) {
+        memset(&p->tune, 0, sizeof p->tune);
+        s = derive(p);
+    }
+    if (s != MCLAHE_SUCCESS) {
+        delete p;
+        return s;
+    }
+    *plan = p;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_plan_destroy(mclahe_plan_t plan)
+{
+    delete plan;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_plan_geometry(mclahe_plan_t p, mclahe_geometry *g)
+{
+    if (!p || !g) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    memset(g, 0, sizeof *g);
+    g->ndim = p->D;
+    for (int i = 0; i < p->D; ++i) {
+        g->pad[i] = p->ax[i].p0 + p->ax[i].p1;
+        g->pad0[i] = p->ax[i].p0;
+        g->pad1[i] = p->ax[i].p1;
+        g->n_kernels_axis[i] = p->ax[i].n;
+    }
+    g->n_kernels = p->nker;
+    g->kernel_voxels = p->K;
+    g->clip_count = p->clipC;
+    g->n_voxels = p->nvox;
+    g->n_cells = p->ncells;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_plan_get_tuning(mclahe_plan_t p, mclahe_tuning *t)
+{
+    if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    t->hist_rows_split = p->v.hCr;
+    t->hist_copies = p->v.hR;
+    t->hist_peel = p->v.hPeel + 1;
+    t->map_rows_split = p->v.mCr;
+    t->map_group = p->v.mG;
+    t->persistent_blocks = p->tune.persistent_blocks;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
+{
+    if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->hist_peel < 0 ||
+        t->hist_peel > 3 || t->persistent_blocks < 0 || t->hist_copies < 0)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "tuning fields must be >= 0 (hist_peel <= 3)");
+    const mclahe_tuning old = p->tune;
+    p->tune = *t;
+    mclahe_status s = derive(p);
+    if (s != MCLAHE_SUCCESS) {
+        const std::string msg = g_err;
+        p->tune = old;
+        derive(p);
+        g_err = msg;
+    }
+    return s;
+}
+
+mclahe_status mclahe_workspace_size(mclahe_plan_t p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    *bytes = p->total;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_workspace_layout(mclahe_plan_t p, mclahe_layout *l)
+{
+    if (!p || !l) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    l->hist = p->o_hist;
+    l->clipped = p->o_clipped;
+    l->lut = p->o_lut;
+    l->range = p->o_range;
+    l->scale = p->o_scale;
+    l->total = p->total;
+    return MCLAHE_SUCCESS;
+}
+
+static mclahe_status check_run_args(const mclahe_plan_s *p, const void *in, void *out, void *ws,
+                                    size_t wsb, size_t need)
+{
+    if (!p) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan is NULL");
+    if (!in || !out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output pointer is NULL");
+    if (((uintptr_t)in % esize(p->in_dt)) || ((uintptr_t)out % esize(p->out_dt)))
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output not aligned to the element size");
+    if (in == out && esize(p->in_dt) != esize(p->out_dt))
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "in-place operation needs equal element sizes");
+    if (!ws || ((uintptr_t)ws % 256)) return fail(MCLAHE_ERROR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (wsb < need)
+        return fail(MCLAHE_ERROR_WORKSPACE, "workspace too small: %zu < %zu bytes", wsb, need);
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run(mclahe_plan_t p, const void *d_in, void *d_out, void *d_ws, size_t wsb, void *stream)
+{
+    g_err.clear();
+    mclahe_status s = check_run_args(p, d_in, d_out, d_ws, wsb, p ? p->total : 0);
+    if (s) return s;
+    McVol v;
+    bind(p, v, d_in, d_out, (char *)d_ws);
+    return run_plain(p, v, (hipStream_t)stream);
+}
+
+mclahe_status mclahe_timer_create(mclahe_timer_t *timer, int max_runs)
+{
+    if (!timer || max_runs < 1 || max_runs > 100000)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "timer needs 1..100000 runs");
+    *timer = nullptr;
+    mclahe_timer_s *t = new (std::nothrow) mclahe_timer_s();
+    if (!t) return fail(MCLAHE_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    t->max_runs = max_runs;
+    t->ev.resize((size_t)max_runs * 5, nullptr);
+    for (auto &e : t->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : t->ev)
+                if (f) (void)hipEventDestroy(f);
+            delete t;
+            return fail(MCLAHE_ERROR_HIP, "hipEventCreate failed");
+        }
+    }
+    *timer = t;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_timer_destroy(mclahe_timer_t t)
+{
+    if (!t) return MCLAHE_SUCCESS;
+    for (auto &e : t->ev) (void)hipEventDestroy(e);
+    delete t;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_timer_reset(mclahe_timer_t t)
+{
+    if (!t) return fail(MCLAHE_ERROR_INVALID_VALUE, "timer is NULL");
+    t->runs = 0;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_timed(mclahe_plan_t p, const void *d_in, void *d_out, void *d_ws, size_t wsb,
+                               void *stream, mclahe_timer_t t)
+{
+    g_err.clear();
+    if (!t) return fail(MCLAHE_ERROR_INVALID_VALUE, "timer is NULL");
+    if (t->runs >= t->max_runs) return fail(MCLAHE_ERROR_INVALID_VALUE, "timer is full (%d runs)", t->max_runs);
+    mclahe_status s = check_run_args(p, d_in, d_out, d_ws, wsb, p ? p->total : 0);
+    if (s) return s;
+    McVol v;
+    bind(p, v, d_in, d_out, (char *)d_ws);
+    s = run_plain(p, v, (hipStream_t)stream, &t->ev[(size_t)t->runs * 5]);
+    if (s == MCLAHE_SUCCESS) t->runs++;
+    return s;
+}
+
+mclahe_status mclahe_timer_read(mclahe_timer_t t, float *pass_ms, int *runs)
+{
+    if (!t || !pass_ms || !runs) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    *runs = t->runs;
+    for (int k = 0; k < 4; ++k) pass_ms[k] = 0.f;
+    if (t->runs == 0) return MCLAHE_SUCCESS;
+    HIPCHK(hipEventSynchronize(t->ev[(size_t)(t->runs - 1) * 5 + 4]));
+    for (int r = 0; r < t->runs; ++r)
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, t->ev[(size_t)r * 5 + k], t->ev[(size_t)r * 5 + k + 1]));
+            pass_ms[k] += ms / t->runs;
+        }
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_batched_workspace_size(int n, const mclahe_plan_t *plans, size_t *bytes)
+{
+    if (!bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    *bytes = L.total;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans, uint64_t *offsets)
+{
+    if (!offsets) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    for (int i = 0; i < n; ++i) offsets[i] = L.vol_off[i];
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                 void *const *d_out, void *d_ws, size_t wsb, void *stream)
+{
+    g_err.clear();
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    if (!d_in || !d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output arrays are NULL");
+    for (int i = 0; i < n; ++i) {
+        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws, wsb, L.total);
+        if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
+    }
+    char *ws = (char *)d_ws;
+    std::vector<char> img;
+    fill_table(n, plans, d_in, d_out, ws, L, img);
+    int want = 0;
+    for (int i = 0; i < n; ++i) want = std::max(want, plans[i]->tune.persistent_blocks);
+    const int grid = persistent_grid(L.lds, want);
+    if (L.lds > 64 * 1024)
+        HIPCHK(hipFuncSetAttribute(mc_persistent_fn(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)L.lds));
+
+    std::string key = std::to_string((uintptr_t)ws) + ":" + std::to_string(grid) + ":" + std::to_string(n);
+    for (int i = 0; i < n; ++i) key += ":" + std::to_string((uintptr_t)plans[i]) + "/" + plan_key(plans[i]);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    GraphEntry *g;
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        g = new GraphEntry();
+        g->bytes = img.size();
+        const int ring = 4;
+        for (int r = 0; r < ring; ++r) {
+            char *h = nullptr;
+            HIPCHK(hipHostMalloc((void **)&h, g->bytes, hipHostMallocDefault));
+            g->host.push_back(h);
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            g->ev.push_back(e);
+            g->used.push_back(false);
+        }
+        memcpy(g->host[0], img.data(), g->bytes);
+        s = build_graph(g, L, ws, grid);
+        if (s) return s;
+        g_graphs[key] = g;
+    } else {
+        g = it->second;
+    }
+    const int slot = g->next;
+    g->next = (g->next + 1) % (int)g->host.size();
+    if (g->used[slot]) HIPCHK(hipEventSynchronize(g->ev[slot]));
+    memcpy(g->host[slot], img.data(), g->bytes);
+    HIPCHK(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, ws + L.o_hdr, g->host[slot], g->bytes,
+                                             hipMemcpyHostToDevice));
+    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    HIPCHK(hipEventRecord(g->ev[slot], (hipStream_t)stream));
+    g->used[slot] = true;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_autotune_workspace_size(mclahe_plan_t p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    const mclahe_tuning saved = p->tune;
+    size_t mx = p->total;
+    for (const mclahe_tuning &t : tune_candidates(p)) {
+        mclahe_tuning tt = t;
+        p->tune = tt;
+        if (derive(p) == MCLAHE_SUCCESS) mx = std::max<size_t>(mx, p->total);
+    }
+    p->tune = saved;
+    derive(p);
+    *bytes = mx;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_autotune(mclahe_plan_t p, const void *d_in, void *d_out, void *d_ws, size_t wsb,
+                              void *stream)
+{
+    g_err.clear();
+    size_t need = 0;
+    mclahe_status s = mclahe_autotune_workspace_size(p, &need);
+    if (s) return s;
+    if ((s = check_run_args(p, d_in, d_out, d_ws, wsb, need))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const mclahe_tuning saved = p->tune;
+    auto time_cfg = [&](const mclahe_tuning &t, float &ms) -> mclahe_status {
+        p->tune = t;
+        mclahe_status r = derive(p);
+        if (r) return r;
+        McVol v;
+        bind(p, v, d_in, d_out, (char *)d_ws);
+        if ((r = run_plain(p, v, st))) return r;   // warm-up
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(e0, st));
+            if ((r = run_plain(p, v, st))) return r;
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float t_ms = 0;
+            HIPCHK(hipEventElapsedTime(&t_ms, e0, e1));
+            best = std::min(best, t_ms);
+        }
+        ms = best;
+        return MCLAHE_SUCCESS;
+    };
+    // histogram knobs first, then the interpolation knobs
+    mclahe_tuning best_t = saved;
+    float best_ms = 1e30f;
+    for (const mclahe_tuning &t : tune_candidates(p)) {
+        float ms;
+        if (time_cfg(t, ms) == MCLAHE_SUCCESS && ms < best_ms) {
+            best_ms = ms;
+            best_t = t;
+        }
+    }
+    p->tune = best_t;
+    derive(p);
+    const int ncl = p->ax[p->D - 1].n - 1;
+    std::vector<int> groups = {1, 2, 4, ncl};
+    for (int g : groups) {
+        if (g < 1 || g > ncl) continue;
+        for (int f : {1, 2, 4}) {
+            mclahe_tuning t = best_t;
+            t.map_group = g;
+            t.map_rows_split = std::max(1, p->v.mCr * f / 2);
+            float ms;
+            if (time_cfg(t, ms) == MCLAHE_SUCCESS && ms < best_ms) {
+                best_ms = ms;
+                best_t = t;
+            }
+        }
+    }
+    p->tune = best_t;
+    derive(p);
+    // store the effective settings
+    mclahe_tuning eff;
+    mclahe_plan_get_tuning(p, &eff);
+    p->tune = eff;
+    derive(p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_store(plan_key(p), eff);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return MCLAHE_SUCCESS;
+}
+
+}  // extern "C"

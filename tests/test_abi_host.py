@@ -1,0 +1,215 @@
+"""Host-side tests of the C-ABI library: no GPU needed.
+
+The library loads and exports every symbol its header declares; plan
+validation, geometry (against the oracle's Eq. 1-2), workspace layout, tuning
+and the argument checks that run before any device call; and the shared
+virtual-padding geometry code against numpy's symmetric padding.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_11355_amd import _lib
+from paper_1906_11355_amd._lib import MclaheError, Plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mclahe.h")
+
+
+def test_library_exports_every_declared_symbol():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(mclahe_[a-z_]+)\s*\(", src))
+    assert len(names) >= 20
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    for s in range(6):
+        assert _lib.status_string(s).startswith("MCLAHE_")
+    assert _lib.version() == "0.1.0"
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(shape=(4,), kernel_size=(5,)), _lib.INVALID_VALUE),
+    (dict(shape=(4,), kernel_size=(0,)), _lib.INVALID_VALUE),
+    (dict(shape=(0,), kernel_size=(1,)), _lib.INVALID_VALUE),
+    (dict(shape=(4, 4), kernel_size=(2,)), _lib.INVALID_VALUE),
+    (dict(shape=(2,) * 9, kernel_size=(1,) * 9), _lib.INVALID_VALUE),
+    (dict(n_bins=1), _lib.INVALID_VALUE),
+    (dict(n_bins=8193), _lib.INVALID_VALUE),
+    (dict(clip_limit=-0.1), _lib.INVALID_VALUE),
+    (dict(clip_limit=float("inf")), _lib.INVALID_VALUE),
+    (dict(clip_limit=float("nan")), _lib.INVALID_VALUE),
+    (dict(mode="kernel", user_range=(0.0, 1.0)), _lib.INVALID_VALUE),
+    (dict(user_range=(1.0, 1.0)), _lib.INVALID_VALUE),
+    (dict(user_range=(0.0, float("inf"))), _lib.INVALID_VALUE),
+])
+def test_plan_validation(kw, status):
+    args = dict(shape=(16, 16), kernel_size=(4, 4), n_bins=64, clip_limit=0.02)
+    args.update(kw)
+    with pytest.raises(MclaheError) as e:
+        Plan(**args)
+    assert e.value.status == status
+    assert str(e.value)
+
+
+def test_unsupported_dtype_rejected():
+    with pytest.raises(TypeError):
+        Plan((8, 8), (4, 4), in_dtype="float64")
+
+
+def test_geometry_matches_oracle():
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        D = int(rng.integers(1, 9))
+        shape = [int(rng.integers(1, 40)) for _ in range(D)]
+        ks = [int(rng.integers(1, s + 1)) for s in shape]
+        p = Plan(shape, ks, 16, 0.3)
+        g = p.geometry()
+        pad, p0, p1, nk = oracle.geometry(shape, ks)
+        assert g["pad"] == pad.tolist() and g["pad0"] == p0.tolist() and g["pad1"] == p1.tolist()
+        assert g["n_kernels_axis"] == nk.tolist()
+        assert g["n_kernels"] == int(np.prod(nk))
+        assert g["kernel_voxels"] == int(np.prod(ks))
+        assert g["clip_count"] == int(np.floor(np.float64(np.float32(0.3)) * np.prod(ks)))
+        assert g["n_cells"] == int(np.prod(nk - 1))
+
+
+def test_workspace_layout_and_tuning():
+    p = Plan((256, 256, 128, 32), (32, 32, 16, 8), 512, 0.02)
+    lay = p.layout()
+    nk, nb = 3645, 512
+    offs = [lay[k] for k in ("hist", "clipped", "lut", "range", "scale")]
+    assert all(o % 256 == 0 for o in offs) and offs == sorted(offs)
+    assert lay["clipped"] - lay["hist"] >= nk * nb * 4
+    assert lay["lut"] - lay["clipped"] >= nk * nb * 8
+    assert lay["range"] - lay["lut"] >= nk * nb * 4
+    assert lay["total"] == p.workspace_size()
+    t = p.tuning()
+    assert t["hist_copies"] in (1, 2, 4, 8) and 1 <= t["hist_peel"] <= 3
+    w0 = p.workspace_size()
+    p.set_tuning(hist_rows_split=t["hist_rows_split"] * 2, hist_copies=4, hist_peel=1,
+                 map_rows_split=7, map_group=1)
+    t2 = p.tuning()
+    assert t2["hist_rows_split"] == t["hist_rows_split"] * 2 and t2["hist_copies"] == 4
+    assert t2["hist_peel"] == 1 and t2["map_group"] == 1 and t2["map_rows_split"] == 7
+    # a split too coarse for the per-unit row table is raised to the minimum
+    q = Plan((256, 256, 128, 32), (32, 32, 16, 8), 512, 0.02)
+    q.set_tuning(map_rows_split=1, hist_rows_split=1)
+    assert q.tuning()["map_rows_split"] == 5 and q.tuning()["hist_rows_split"] == 5
+    assert p.workspace_size() > w0          # more histogram partials
+    with pytest.raises(MclaheError):
+        p.set_tuning(hist_copies=3)
+    assert p.tuning() == t2                 # a rejected tuning leaves the plan unchanged
+    assert p.autotune_workspace_size() >= p.workspace_size()
+
+
+def test_adaptive_layout_has_per_kernel_ranges():
+    p = Plan((64, 64, 32), (16, 16, 8), 256, 0.02, "kernel")
+    lay = p.layout()
+    nk = p.geometry()["n_kernels"]
+    assert lay["scale"] - lay["range"] >= nk * 2 * 4
+    assert lay["total"] - lay["scale"] >= nk * 4
+
+
+def test_run_argument_checks_before_device_calls():
+    p = Plan((64, 64), (16, 16), 64, 0.02)
+    need = p.workspace_size()
+    with pytest.raises(MclaheError) as e:
+        p.run_ptr(0, 256, 256, need)
+    assert e.value.status == _lib.INVALID_VALUE
+    with pytest.raises(MclaheError) as e:
+        p.run_ptr(256, 512, 4096, need - 1)
+    assert e.value.status == _lib.WORKSPACE
+    with pytest.raises(MclaheError) as e:
+        p.run_ptr(256, 512, 4096 + 4, need)
+    assert e.value.status == _lib.WORKSPACE
+    with pytest.raises(MclaheError) as e:
+        p.run_ptr(258, 512, 4096, need)        # float input not 4-byte aligned
+    assert e.value.status == _lib.INVALID_VALUE
+    q = Plan((64, 64), (16, 16), 64, 0.02, in_dtype="uint8", out_dtype="float32")
+    with pytest.raises(MclaheError):
+        q.run_ptr(256, 256, 4096, q.workspace_size())   # in-place with different sizes
+
+
+def test_batched_workspace_offsets():
+    plans = [Plan((64, 64), (16, 16), 64, 0.02), Plan((32, 32, 16), (8, 8, 4), 128, 0.01, "kernel"),
+             Plan((16, 16, 8, 8), (4, 4, 4, 4), 256, 0.05, in_dtype="uint16")]
+    total = _lib.batched_workspace_size(plans)
+    offs = _lib.batched_workspace_offsets(plans)
+    assert all(o % 256 == 0 for o in offs) and offs == sorted(offs)
+    for o, o2, p in zip(offs, offs[1:] + [total], plans):
+        assert o2 - o >= p.workspace_size()
+
+
+def test_plan_count_limits():
+    with pytest.raises(MclaheError):
+        Plan((2 ** 20, 2 ** 20), (2 ** 19, 2 ** 19), 16, 0.1)   # kernel voxels >= 2^32
+
+
+# ------------------------------------------ shared padding geometry (g++)
+@pytest.fixture(scope="module")
+def probe():
+    d = tempfile.mkdtemp(prefix="mclahe_probe_")
+    so = os.path.join(d, "probe.so")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC",
+                           "-I", os.path.join(ROOT, "paper_1906_11355_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "geom_probe.cpp"), "-o", so])
+    lib = ctypes.CDLL(so)
+    for f in (lib.probe_kernel_box, lib.probe_cell_range):
+        f.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_int)]
+        f.restype = None
+    return lib
+
+
+def test_kernel_footprints_match_numpy_symmetric_padding(probe):
+    """Every kernel's box and multiplicities equal the counts of original
+    coordinates in its window of np.pad(arange(s), mode='symmetric')."""
+    rng = np.random.default_rng(1)
+    cases = [(s, b) for s in range(1, 30) for b in range(1, s + 1)]
+    cases += [(int(s), int(rng.integers(1, s + 1))) for s in rng.integers(30, 3000, 200)]
+    out = (ctypes.c_int * 4)()
+    for s, b in cases:
+        p = 2 * b - 1 - ((s - 1) % b)
+        p0, p1 = p // 2, (p + 1) // 2
+        padded = np.pad(np.arange(s), (p0, p1), mode="symmetric")
+        n = padded.size // b
+        for k in range(n):
+            probe.probe_kernel_box(s, b, p0, p1, k, out)
+            lo, hi, olo, ohi = out
+            cnt = np.bincount(padded[k * b:(k + 1) * b], minlength=s)
+            mult = np.zeros(s, int)
+            mult[lo:hi] = 1
+            mult[olo:ohi] += 1
+            assert (cnt == mult).all(), (s, b, k, (lo, hi, olo, ohi))
+
+
+def test_interpolation_cells_partition_the_axis(probe):
+    rng = np.random.default_rng(2)
+    cases = [(s, b) for s in range(1, 25) for b in range(1, s + 1)]
+    cases += [(int(s), int(rng.integers(1, s + 1))) for s in rng.integers(25, 3000, 200)]
+    out = (ctypes.c_int * 3)()
+    for s, b in cases:
+        p = 2 * b - 1 - ((s - 1) % b)
+        p0, p1 = p // 2, (p + 1) // 2
+        n = (s + p) // b
+        owner = np.full(s, -1)
+        for c in range(n - 1):
+            probe.probe_cell_range(s, b, p0, p1, c, out)
+            lo, hi, m0 = out
+            if lo < hi:
+                assert (owner[lo:hi] == -1).all()
+                owner[lo:hi] = c
+                assert 0 <= m0 < 2 * b
+        x = np.arange(s)
+        m = 2 * (x + p0) - (b - 1)
+        assert (owner == m // (2 * b)).all(), (s, b)

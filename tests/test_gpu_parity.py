@@ -1,0 +1,186 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Histograms and clipped counts must be bit-exact; LUTs and float outputs within
+1e-5 (of the [0, 1] full scale), integer outputs within one level.  Cases span
+several work units with ragged tails, every dimensionality 1..8, every dtype,
+both range modes, user ranges, the degenerate cases of the method and the
+work-decomposition regimes of the kernels.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _case(x, ks, nb, clip, mode="global", out_dtype=np.float32, user_range=None, tuning=None, **kw):
+    r = oracle_run(x, ks, nb, clip, mode, user_range, out_dtype)
+    g = gpu_run(x, ks, nb, clip, mode, user_range, out_dtype, tuning=tuning, **kw)
+    assert_parity(g, r, out_dtype, what=f"shape={x.shape} ks={ks} nb={nb} clip={clip} {mode} {x.dtype}->{np.dtype(out_dtype)}")
+    return g, r
+
+
+# ------------------------------------------------------------ worked example
+def test_worked_example_1d():
+    gold = json.load(open(os.path.join(HERE, "golden", "worked_1d.json")))
+    x = np.array(gold["input"], np.float32)
+    from fractions import Fraction
+    for c in gold["cases"]:
+        mode = "kernel" if c["adaptive"] else "global"
+        g, _ = _case(x, gold["kernel_size"], gold["n_bins"], c["clip"], mode)
+        assert g["hist"].tolist() == c["hist"]
+        assert g["clipped"].tolist() == c["clipped_times_n"]
+        np.testing.assert_allclose(g["out"], [float(Fraction(v)) for v in c["out"]], atol=1e-6)
+
+
+# ------------------------------------------------------------- random small
+def _rand_case(seed):
+    rng = np.random.default_rng(seed)
+    D = int(rng.integers(1, 5))
+    shape = [int(rng.integers(1, [400, 60, 24, 12][D - 1] + 1)) for _ in range(D)]
+    ks = [int(rng.integers(1, s + 1)) for s in shape]
+    dt = [np.uint8, np.uint16, np.float32][int(rng.integers(0, 3))]
+    kind = int(rng.integers(0, 4))
+    if kind == 0:
+        x = rng.integers(0, 3, size=shape)
+    elif kind == 1:
+        x = rng.poisson(3.0, size=shape)
+    elif kind == 2:
+        x = rng.integers(0, 50000 if dt == np.uint16 else 255, size=shape)
+    else:
+        x = rng.normal(100, 30, size=shape).clip(0)
+    x = x.astype(dt) if dt != np.float32 else (x * rng.choice([1.0, 0.13, -3.0])).astype(np.float32)
+    nb = int(rng.choice([2, 5, 64, 256, 512]))
+    clip = float(rng.choice([0.0, 0.01, 0.02, 0.25, 1.0, 3.0]))
+    mode = ["global", "kernel"][int(rng.integers(0, 2))]
+    out = [np.float32, np.uint8, np.uint16][int(rng.integers(0, 3))]
+    return np.ascontiguousarray(x), ks, nb, clip, mode, out
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_small(seed):
+    x, ks, nb, clip, mode, out = _rand_case(seed)
+    _case(x, ks, nb, clip, mode, out)
+
+
+@pytest.mark.parametrize("D", [5, 6, 7, 8])
+def test_high_dimensional_generic_path(D):
+    rng = np.random.default_rng(D)
+    shape = [int(rng.integers(2, 6)) for _ in range(D)]
+    shape[-1] = 7
+    ks = [int(rng.integers(1, s + 1)) for s in shape]
+    x = rng.poisson(4.0, size=shape).astype(np.float32)
+    for mode in ("global", "kernel"):
+        _case(x, ks, 16, 0.1, mode)
+
+
+def test_large_bins_generic_map():
+    rng = np.random.default_rng(3)
+    x = rng.gamma(2.0, 100.0, size=(14, 12, 10, 9)).astype(np.float32)
+    _case(x, (5, 4, 3, 4), 2048, 0.02, "global")
+    _case(x, (5, 4, 3, 4), 1024, 0.02, "kernel")
+
+
+# --------------------------------------------------- decomposition regimes
+def test_long_last_axis_split_kernels():
+    """Kernels longer than one work-group row: split histogram and cell parts."""
+    rng = np.random.default_rng(4)
+    x = rng.integers(0, 256, size=(6, 4096)).astype(np.uint8)
+    _case(x, (3, 4096), 256, 0.01, "global")
+    _case(x, (3, 4096), 256, 0.01, "kernel")
+    y = rng.poisson(5.0, size=(5, 3000)).astype(np.float32)
+    _case(y, (2, 1500), 64, 0.05, "global")
+    _case(y, (5, 2999), 64, 0.05, "kernel")
+
+
+def test_unaligned_pointers_and_rows():
+    rng = np.random.default_rng(5)
+    x = rng.poisson(5.0, size=(33, 47, 19)).astype(np.float32)    # rows not multiple of 4
+    _case(x, (8, 10, 5), 128, 0.03)
+    y = rng.poisson(5.0, size=(40, 64)).astype(np.float32)
+    _case(y, (9, 16), 128, 0.03, in_offset=4, out_offset=8)       # misaligned buffers
+    z = rng.integers(0, 256, size=(40, 64)).astype(np.uint8)
+    _case(z, (9, 16), 256, 0.03, in_offset=1, out_offset=4)
+
+
+def test_in_place():
+    rng = np.random.default_rng(6)
+    x = rng.poisson(5.0, size=(30, 40, 20)).astype(np.float32)
+    _case(x, (7, 9, 6), 64, 0.02, inplace=True)
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(hist_copies=1, hist_peel=1), dict(hist_copies=4, hist_peel=3, hist_rows_split=1),
+    dict(hist_copies=8, hist_peel=2, hist_rows_split=37), dict(map_group=1, map_rows_split=1),
+    dict(map_group=3, map_rows_split=11), dict(hist_copies=2, map_group=2, map_rows_split=64)])
+def test_tuning_does_not_change_bits(tuning):
+    rng = np.random.default_rng(7)
+    x = rng.poisson(2.0, size=(40, 36, 30, 16)).astype(np.float32)
+    base = gpu_run(x, (8, 8, 6, 4), 128, 0.02)
+    g = gpu_run(x, (8, 8, 6, 4), 128, 0.02, tuning=tuning)
+    for k in ("out", "hist", "clipped", "lut", "range"):
+        np.testing.assert_array_equal(g[k], base[k], err_msg=f"{k} changed under {tuning}")
+
+
+def test_deterministic():
+    rng = np.random.default_rng(8)
+    x = rng.poisson(1.0, size=(64, 64, 32)).astype(np.float32)
+    a = gpu_run(x, (16, 16, 8), 256, 0.02, "kernel")
+    b = gpu_run(x, (16, 16, 8), 256, 0.02, "kernel")
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+# ------------------------------------------------------------ degenerate
+@pytest.mark.parametrize("mode", ["global", "kernel"])
+def test_constant_input(mode):
+    x = np.full((20, 30, 12), 7.5, np.float32)
+    g, _ = _case(x, (5, 7, 4), 32, 0.02, mode)
+    assert (g["out"] == 0).all()
+
+
+def test_user_range_and_clamping():
+    rng = np.random.default_rng(9)
+    x = rng.normal(0, 2, size=(50, 70)).astype(np.float32)
+    _case(x, (10, 12), 64, 0.05, user_range=(-1.0, 1.5))
+    _case(x, (10, 12), 64, 0.05, user_range=(float(x.min()), float(x.max())))
+
+
+def test_adversarial_collisions():
+    x = np.zeros((64, 64, 16), np.float32)
+    x[0, 0, 0] = 1.0                      # all but one voxel in bin 0
+    _case(x, (16, 16, 8), 256, 0.5)
+    y = np.tile(np.array([0.0, 1.0], np.float32), (32, 32, 8))   # two alternating bins
+    _case(y, (8, 8, 4), 256, 0.01, "kernel")
+
+
+def test_extreme_values():
+    rng = np.random.default_rng(10)
+    big = (3e38 - rng.integers(0, 1000, size=(20, 24)).astype(np.float64) * 1e32).astype(np.float32)
+    _case(big, (5, 6), 64, 0.1)
+    both = rng.choice(np.array([-3e38, 0.0, 3e38], np.float32), size=(20, 24))   # hi - lo = inf
+    _case(both, (5, 6), 64, 0.1)
+    den = (rng.integers(0, 50, size=(20, 24)) * 1e-42).astype(np.float32)        # denormals
+    _case(den, (5, 6), 64, 0.1)
+    _case(den, (5, 6), 64, 0.1, "kernel")
+    z = rng.choice(np.array([-0.0, 0.0, 1.0], np.float32), size=(20, 24))        # signed zeros
+    _case(z, (5, 6), 8, 0.1, "kernel")
+
+
+# ------------------------------------------------------------ full sizes
+def test_cfg1_2d_u8_full():
+    from paper_1906_11355_amd import synth
+    x = synth.gen_2d((512, 512), 1)
+    _case(x, (64, 64), 256, 0.01, "global")
+    _case(x, (64, 64), 256, 0.01, "global", out_dtype=np.uint8)
+
+
+def test_cfg2_3d_f32_ahr_full():
+    from paper_1906_11355_amd import synth
+    x = synth.gen_3d((256, 256, 128), 2)
+    _case(x, (32, 32, 16), 256, 0.02, "kernel")
