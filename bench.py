@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--batched", action="store_true",
-                    help="also time the mixed-batch persistent launch vs plain launches")
+                    help="also time the mixed batch: batched launches vs per-volume launches")
     return ap.parse_args()
 
 
@@ -165,7 +165,7 @@ def main():
 
 
 def bench_batched(torch, np, _lib, synth, dev, n=None):
-    """Mixed batch: one persistent launch vs plain per-volume launches."""
+    """Mixed batch: one launch per pass for all volumes vs per-volume launches."""
     specs = synth.mix_spec(64, 4)
     if n:
         specs = specs[:n]

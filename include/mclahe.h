@@ -113,11 +113,11 @@ typedef struct {
  *                       2 = one round, 3 = two rounds (0 = default)
  *   map_rows_split    : row chunks per cell column in the interpolation pass
  *   map_group         : interpolation cells per work unit along the last axis
- *   persistent_blocks : grid size of the persistent batched kernel          */
+ *   reserved          : must be 0                                           */
 typedef struct {
     int32_t hist_rows_split, hist_copies, hist_peel;
     int32_t map_rows_split, map_group;
-    int32_t persistent_blocks;
+    int32_t reserved;
 } mclahe_tuning;
 
 /* Create a plan (host only; no device call).  Arguments follow the paper's
@@ -164,7 +164,7 @@ mclahe_status mclahe_run(mclahe_plan_t plan, const void *d_in, void *d_out,
                          void *d_workspace, size_t workspace_bytes, void *hip_stream);
 
 /* Workspace bytes for a batched call over n plans (sum of the per-volume
- * workspaces plus the work-queue header and descriptor table).             */
+ * workspaces plus the descriptor table).                                    */
 mclahe_status mclahe_batched_workspace_size(int n, const mclahe_plan_t *plans, size_t *bytes);
 
 /* Per-volume workspace offsets inside a batched workspace: offsets[i] is the
@@ -173,14 +173,27 @@ mclahe_status mclahe_batched_workspace_size(int n, const mclahe_plan_t *plans, s
 mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans,
                                                uint64_t *offsets);
 
-/* Enhance n independent volumes (mixed ndim, shape, dtype, parameters) with
- * ONE persistent fused kernel launch, replayed from a cached hipGraph.  Each
- * output is bit-identical to mclahe_run of the same plan.  The plans must
- * stay alive until the work has completed on the stream.                    */
+/* Enhance n independent volumes (mixed ndim, shape, dtype, parameters) as
+ * one batch: each of the four passes is ONE launch over the work units of
+ * every volume, and the four launches are replayed from a hipGraph cached
+ * per batch signature (plans and workspace address), after one stream-ordered
+ * copy of the batch's descriptor table into the workspace.  Each output (and
+ * each intermediate array) is bit-identical to mclahe_run of the same plan.
+ * The plans must stay alive until the work has completed on the stream.    */
 mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans,
                                  const void *const *d_in, void *const *d_out,
                                  void *d_workspace, size_t workspace_bytes,
                                  void *hip_stream);
+
+/* Host image of the batch descriptor table that mclahe_run_batched would
+ * upload for these arguments (no device call), for inspection and tests.
+ * Copies min(image_bytes, *needed) bytes to host_image (may be NULL) and
+ * stores the table size in *needed.  The image holds the library's internal
+ * batch header, per-pass unit prefix sums and volume descriptors.           */
+mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans,
+                                   const void *const *d_in, void *const *d_out,
+                                   void *d_workspace, void *host_image,
+                                   size_t image_bytes, size_t *needed);
 
 /* Autotune the plan's work decomposition on the current device: times the
  * candidate settings on the given buffers (which it overwrites) and keeps

@@ -41,7 +41,7 @@ class Geometry(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("hist_rows_split", "hist_copies", "hist_peel",
-                                                "map_rows_split", "map_group", "persistent_blocks")]
+                                                "map_rows_split", "map_group", "reserved")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -50,6 +50,14 @@ class Tuning(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1906_11355_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname.  Load it first
+    # so that the library binds to the runtime that owns torch's streams and
+    # allocations: one HIP runtime per process (a stream handle is only valid
+    # in the runtime that created it).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i64p = ctypes.POINTER(ctypes.c_int64)
@@ -67,6 +75,8 @@ def _load():
         "mclahe_batched_workspace_offsets": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_uint64)],
         "mclahe_run_batched": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
                                ctypes.c_size_t, P],
+        "mclahe_batched_table": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
+                                 P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_autotune_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_autotune": [P, P, P, P, ctypes.c_size_t, P],
         "mclahe_timer_create": [ctypes.POINTER(P), ctypes.c_int],
@@ -238,6 +248,19 @@ def run_batched_ptr(plans, d_ins, d_outs, d_ws: int, ws_bytes: int, stream: int 
     ins = (ctypes.c_void_p * n)(*d_ins)
     outs = (ctypes.c_void_p * n)(*d_outs)
     _check(lib.mclahe_run_batched(n, _plans_array(plans), ins, outs, d_ws, ws_bytes, stream))
+
+
+def batched_table(plans, d_ins, d_outs, d_ws: int) -> bytes:
+    """Host image of the descriptor table of a batched call (no device call)."""
+    n = len(plans)
+    ins = (ctypes.c_void_p * n)(*d_ins)
+    outs = (ctypes.c_void_p * n)(*d_outs)
+    need = ctypes.c_size_t()
+    _check(lib.mclahe_batched_table(n, _plans_array(plans), ins, outs, d_ws, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib.mclahe_batched_table(n, _plans_array(plans), ins, outs, d_ws, buf, need.value,
+                                    ctypes.byref(need)))
+    return buf.raw
 
 
 def version() -> str:

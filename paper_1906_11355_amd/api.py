@@ -77,7 +77,7 @@ def make_plans(xs: Sequence[torch.Tensor], params: Sequence[dict]) -> list:
 
 def enhance_batched(xs: Sequence[torch.Tensor], params: Sequence[dict] | None = None, plans=None,
                     outs=None, workspace: torch.Tensor | None = None, return_workspace: bool = False):
-    """Enhance many volumes with one persistent fused launch (hipGraph)."""
+    """Enhance many volumes as one batch: one launch per pass over all volumes (hipGraph)."""
     if plans is None:
         plans = make_plans(xs, params)
     for x in xs:

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmclahe.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["mclahe.hip", "k_plain_f32.hip", "k_plain_u16.hip", "k_plain_u8.hip", "k_persist.hip"]
+SOURCES = ["mclahe.hip", "k_plain_f32.hip", "k_plain_u16.hip", "k_plain_u8.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

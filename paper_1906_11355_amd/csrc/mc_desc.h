@@ -1,7 +1,7 @@
 // Volume descriptor and geometry helpers shared by the host runtime and the
 // gfx950 kernels of the MCLAHE library.  Plain-old-data only: the same struct
 // is passed by value to the per-pass kernels and stored in a device table for
-// the persistent batched kernel.
+// the batched kernels.
 #pragma once
 #include <stdint.h>
 
@@ -85,6 +85,18 @@ MC_HD int32_t mc_cell_m(const McAxis &a, int32_t c, int32_t x)
     return 2 * (x + a.p0) - (a.b - 1) - 2 * a.b * c;
 }
 
+// LDS stride (floats) of one bin's row in the staged GHR LUTs: nlk last-axis
+// kernels x NO outer corners, padded to an odd number of read units (16-byte
+// reads when NO >= 4) so that lanes reading different bins hit different
+// bank groups.
+MC_HD int32_t mc_lut_stride(int32_t nlk, int32_t NO)
+{
+    const int32_t cw = NO >= 4 ? 4 : NO;
+    int32_t q = nlk * NO / cw;
+    if ((q & 1) == 0) q += 1;
+    return q * cw;
+}
+
 // Everything the kernels need about one volume.
 struct McVol {
     // ---- problem -----------------------------------------------------------
@@ -122,20 +134,47 @@ struct McVol {
     float *scale;             // GHR: [1]; AHR: [nker]
 };
 
-// Header of the persistent batched kernel's work queue (device memory).
-// Tickets are handed out in phase-major order: all range units of all
-// volumes, then all histogram units, then clip units, then map units.
+// Batched descriptor table (device memory, uploaded per call): a header, one
+// record per batched launch, the launches' index arrays, then the volume
+// descriptors.  A batched launch runs one pass for every volume of one kernel
+// class (the template instance the per-volume path would launch).
 #define MC_PHASES 4
-struct McQueue {
-    uint32_t head;                 // next ticket
-    uint32_t error;                // set if a bounded wait expired
-    uint32_t pad_[2];
+struct McBatchHdr {
+    uint32_t nvol, nlaunch, pad_[2];
+};
+struct McLaunchRec {
+    uint32_t phase;    // 0 range, 1 histogram, 2 clip/CDF, 3 map
+    uint32_t n;        // volumes in this launch
+    uint32_t list;     // offset (in uint32) of the volume index list [n]
+    uint32_t pre;      // offset (in uint32) of the unit prefix sums [n + 1]
+    uint32_t units;    // work-groups of the launch (= pre[n])
+    uint32_t pad_[3];
 };
 
-// Device table: header, per-phase per-volume ticket prefix sums, volumes.
-struct McBatch {
-    uint32_t nvol, total;
-    uint32_t phase_start[MC_PHASES + 1];
-    uint32_t spin_limit;
-    uint32_t pad_;
+// What a batched kernel receives (by value).
+struct McBatchSrc {
+    const McVol *vols;
+    const uint32_t *list;
+    const uint32_t *pre;
+    uint32_t n, pad_;
 };
+
+// Units of pass ph of a volume: 0 range, 1 histogram, 2 clip/CDF, 3 map.
+MC_HD uint32_t mc_phase_units(const McVol &v, int ph)
+{
+    return ph == 0 ? (v.mode == MC_AHR ? v.n_hist_wu : v.n_range_wu)
+         : ph == 1 ? v.n_hist_wu : ph == 2 ? v.n_clip_wu : v.n_map_wu;
+}
+
+// Entry j owning unit r of a launch: the largest j with pre[j] <= r, where
+// pre holds the prefix sums of the units (pre[0] = 0, pre[n] = all units).
+MC_HD uint32_t mc_batch_volume(const uint32_t *pre, uint32_t n, uint32_t r)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (pre[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}

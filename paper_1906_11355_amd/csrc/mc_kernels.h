@@ -2,8 +2,8 @@
 //
 // Every pass is written as a "work unit" device function that a work-group of
 // MC_T = 256 threads (4 wave64s) executes.  The per-pass kernels launch one
-// work-group per unit; the persistent batched kernel pulls units of many
-// volumes from a queue and calls the very same functions, so both paths
+// work-group per unit; the batched kernels launch one work-group per unit of
+// every volume of a batch and call the very same functions, so both paths
 // produce bit-identical results.
 //
 // Passes (Algorithm 1 of Stimper et al.; Sec. III.C-D):
@@ -567,13 +567,36 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int64_t so = rpi / rs.in_len;
         const int sr = (int)(rpi - so * rs.in_len);
         const int64_t xoff = (int64_t)(c_lo + tch) * V;
-        for (int64_t row = rstart; row < r1; row += rpi) {
-            const HistOTab te = L.otab[o - o0];
-            const int xin = rs.in_lo + r;
-            const int64_t off = te.off + (int64_t)xin * rs.in_stride + xoff;
-            float f[V];
-            load_chunk<Tin, V>(in + off, f);
-            const uint32_t wrow = te.w * (uint32_t)mc_mult(ib, xin);
+        // U rows per step: all their loads are issued before any is used, so
+        // each wave keeps U wide loads in flight
+        constexpr int U = V >= 8 ? 2 : 4;
+        for (int64_t row = rstart; row < r1; row += (int64_t)U * rpi) {
+            int64_t offs[U];
+            uint32_t wrs[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ok[u] = row + (int64_t)u * rpi < r1;
+                const HistOTab te = L.otab[ok[u] ? (int)(o - o0) : 0];
+                const int xin = rs.in_lo + r;
+                offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
+                wrs[u] = te.w * (uint32_t)mc_mult(ib, xin);
+                r += sr;
+                o += so;
+                if (r >= rs.in_len) {
+                    r -= rs.in_len;
+                    o += 1;
+                }
+            }
+            float fu[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+            if (!ok[u]) break;
+            const float (&f)[V] = fu[u];
+            const uint32_t wrow = wrs[u];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 if constexpr (RANGE_ONLY) {
@@ -607,11 +630,6 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                     }
                 }
             }
-            r += sr;
-            o += so;
-            if (r >= rs.in_len) {
-                r -= rs.in_len;
-                o += 1;
             }
         }
     }
@@ -740,10 +758,13 @@ __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int
     rowspace_finish(d, rs);
 }
 
-// Weight of x towards the upper kernel of its cell c along axis a.
+// Weight of x towards the upper kernel of its cell c along axis a,
+// m / (2b) as m times the single-precision reciprocal of 2b (exact for
+// power-of-two b, otherwise within one ulp; the same expression is used by
+// every kernel, so plain and batched results stay bit-identical).
 __device__ __forceinline__ float cell_weight(const McAxis &a, int c, int x)
 {
-    return __fdiv_rn((float)mc_cell_m(a, c, x), (float)(2 * a.b));
+    return (float)mc_cell_m(a, c, x) * (1.0f / (float)(2 * a.b));
 }
 
 template <int D>
@@ -800,8 +821,11 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
 #pragma unroll
     for (int i = 0; i < D - 1; ++i) kbase += (int64_t)cidx[i] * kst[i];
 
-    // stage LUTs: GHR [bin][lk][corner'], AHR [lk*NO + corner'][bin]
+    // stage LUTs.  GHR: one row of SB floats per bin holding [lk][corner'],
+    // SB padded to an odd number of LDS read units so that lanes reading
+    // different bins spread over the banks.  AHR: [lk*NO + corner'][bin].
     const int nlk = ncl + 1;
+    const int SB = AHR ? 0 : mc_lut_stride(nlk, NO);
     const int tot = nb * nlk * NO;
     for (int i = threadIdx.x; i < tot; i += MC_T) {
         const int b = i % nb;
@@ -813,7 +837,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             if ((co >> (D - 2 - j)) & 1) kid += kst[j];
         const float v = d.lut[kid * nb + b];
         if constexpr (AHR) lut[i] = v;
-        else lut[(b * nlk + lk) * NO + co] = v;
+        else lut[b * SB + lk * NO + co] = v;
     }
     // per-corner ranges (AHR: one last-axis cell per unit)
     float clo[NC], csc[NC];
@@ -876,7 +900,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int tch = threadIdx.x % cpr, trow = threadIdx.x / cpr;
     if (!(trow < rpi)) return;
     const int64_t xoff = (int64_t)(c_lo + tch) * V;
-    int cl[V];
+    int lbase[V];      // LDS offset of the voxel's last-axis kernel pair
     float wl[V];
     bool val[V];
     bool allv = true;
@@ -891,7 +915,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             const int m = 2 * (x + al.p0) - (al.b - 1);
             c = m / (2 * al.b);
         }
-        cl[e] = c - cA;
+        lbase[e] = (c - cA) * NO;
         wl[e] = val[e] ? cell_weight(al, c, x) : 0.f;
     }
     const Tin *in = (const Tin *)d.in;
@@ -903,84 +927,105 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
     const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
-    for (int64_t row = rstart; row < r1; row += rpi) {
-        const OT &te = otab[o - o0];
-        const int xin = rs.in_lo + r;
-        const int64_t off = te.off + (int64_t)xin * rs.in_stride + xoff;
-        float f[V];
-        load_chunk<Tin, V>(in + off, f);
-        float rc[NO];
-        if constexpr (D == 1) {
-            rc[0] = 1.0f;
-        } else {
-            const float w = cell_weight(d.ax[D - 2], cidx[D - 2], xin);
-            const float omw = 1.0f - w;
+    // rows whose loads are in flight together; the staged LUTs bound this
+    // kernel's occupancy, so registers are spent on memory parallelism
+    constexpr int U = V >= 8 ? 4 : 8;
+    for (int64_t row = rstart; row < r1; row += (int64_t)U * rpi) {
+        int64_t offs[U];
+        float win[U];
+        float cfu[U][NOH];
+        bool ok[U];
 #pragma unroll
-            for (int q = 0; q < NOH; ++q) {
-                const float cq = D >= 3 ? te.coef[q] : 1.0f;
-                rc[2 * q] = cq * omw;
-                rc[2 * q + 1] = cq * w;
+        for (int u = 0; u < U; ++u) {
+            ok[u] = row + (int64_t)u * rpi < r1;
+            const OT &te = otab[ok[u] ? (int)(o - o0) : 0];
+            const int xin = rs.in_lo + r;
+            offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
+            win[u] = D >= 2 ? cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xin) : 0.f;
+#pragma unroll
+            for (int q = 0; q < NOH; ++q) cfu[u][q] = D >= 3 ? te.coef[q] : 1.0f;
+            r += sr;
+            o += so;
+            if (r >= rs.in_len) {
+                r -= rs.in_len;
+                o += 1;
             }
         }
-        float y[V];
+        float fu[U][V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            float Lv[NC];
-            if constexpr (AHR) {
+        for (int u = 0; u < U; ++u)
+            if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    Lv[c] = lut[c * nb + bin_of(f[e], clo[c], csc[c], nbf, nbm1)];
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) break;
+            float rc[NO];
+            if constexpr (D == 1) {
+                rc[0] = 1.0f;
             } else {
-                const int b = bin_of(f[e], glo, gsc, nbf, nbm1);
-                const float *p = lut + (b * nlk + cl[e]) * NO;
-                if constexpr (NO % 4 == 0) {
+                const float w = win[u];
+                const float omw = 1.0f - w;
 #pragma unroll
-                    for (int c = 0; c < NC; c += 4) {
-                        const float4 q = *reinterpret_cast<const float4 *>(p + c);
-                        Lv[c] = q.x;
-                        Lv[c + 1] = q.y;
-                        Lv[c + 2] = q.z;
-                        Lv[c + 3] = q.w;
-                    }
-                } else if constexpr (NO % 2 == 0) {
+                for (int q = 0; q < NOH; ++q) {
+                    rc[2 * q] = cfu[u][q] * omw;
+                    rc[2 * q + 1] = cfu[u][q] * w;
+                }
+            }
+            float y[V];
 #pragma unroll
-                    for (int c = 0; c < NC; c += 2) {
-                        const float2 q = *reinterpret_cast<const float2 *>(p + c);
-                        Lv[c] = q.x;
-                        Lv[c + 1] = q.y;
-                    }
+            for (int e = 0; e < V; ++e) {
+                const float fe = fu[u][e];
+                float Lv[NC];
+                if constexpr (AHR) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        Lv[c] = lut[c * nb + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
                 } else {
+                    const int b = bin_of(fe, glo, gsc, nbf, nbm1);
+                    const float *p = lut + b * SB + lbase[e];
+                    if constexpr (NO % 4 == 0) {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) Lv[c] = p[c];
+                        for (int c = 0; c < NC; c += 4) {
+                            const float4 q = *reinterpret_cast<const float4 *>(p + c);
+                            Lv[c] = q.x;
+                            Lv[c + 1] = q.y;
+                            Lv[c + 2] = q.z;
+                            Lv[c + 3] = q.w;
+                        }
+                    } else if constexpr (NO % 2 == 0) {
+#pragma unroll
+                        for (int c = 0; c < NC; c += 2) {
+                            const float2 q = *reinterpret_cast<const float2 *>(p + c);
+                            Lv[c] = q.x;
+                            Lv[c + 1] = q.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) Lv[c] = p[c];
+                    }
                 }
-            }
-            float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
+                float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
 #pragma unroll
-            for (int c = 1; c < NO; ++c) {
-                A = __fmaf_rn(rc[c], Lv[c], A);
-                B = __fmaf_rn(rc[c], Lv[NO + c], B);
-            }
-            y[e] = __fmaf_rn(wl[e], B - A, A);
-        }
-        if (vecst) {
-            if constexpr (V % 4 == 0) {
-                f4 *op = (f4 *)((float *)d.out + off);
-#pragma unroll
-                for (int q = 0; q < V / 4; ++q) {
-                    f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
-                    __builtin_nontemporal_store(t, op + q);
+                for (int c = 1; c < NO; ++c) {
+                    A = __fmaf_rn(rc[c], Lv[c], A);
+                    B = __fmaf_rn(rc[c], Lv[NO + c], B);
                 }
+                y[e] = __fmaf_rn(wl[e], B - A, A);
             }
-        } else {
+            const int64_t off = offs[u];
+            if (vecst) {
+                if constexpr (V % 4 == 0) {
+                    f4 *op = (f4 *)((float *)d.out + off);
 #pragma unroll
-            for (int e = 0; e < V; ++e)
-                if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
-        }
-        r += sr;
-        o += so;
-        if (r >= rs.in_len) {
-            r -= rs.in_len;
-            o += 1;
+                    for (int q = 0; q < V / 4; ++q) {
+                        f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                        __builtin_nontemporal_store(t, op + q);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
+            }
         }
     }
 }

@@ -3,18 +3,20 @@
 #pragma once
 #include "mc_desc.h"
 
-typedef void (*KFn)(McVol);
+typedef void (*KFn)(McVol);         // per-volume kernel: one volume by value
+typedef void (*KFnB)(McBatchSrc);   // batched twin: many volumes of one class
 
-KFn mc_pick_range_u8();
-KFn mc_pick_range_u16();
-KFn mc_pick_range_f32();
-KFn mc_pick_hist_u8(bool ahr, bool ro, int peel);
-KFn mc_pick_hist_u16(bool ahr, bool ro, int peel);
-KFn mc_pick_hist_f32(bool ahr, bool ro, int peel);
-KFn mc_pick_map_u8(int D, bool ahr, int path);
-KFn mc_pick_map_u16(int D, bool ahr, int path);
-KFn mc_pick_map_f32(int D, bool ahr, int path);
+struct KPair {
+    KFn plain;
+    KFnB batch;
+};
 
-// Persistent batched kernel (k_persist.hip): host-side kernel handles.
-const void *mc_persistent_fn();
-const void *mc_zero_fn();
+KPair mc_pick_range_u8();
+KPair mc_pick_range_u16();
+KPair mc_pick_range_f32();
+KPair mc_pick_hist_u8(bool ahr, bool ro, int peel);
+KPair mc_pick_hist_u16(bool ahr, bool ro, int peel);
+KPair mc_pick_hist_f32(bool ahr, bool ro, int peel);
+KPair mc_pick_map_u8(int D, bool ahr, int path);
+KPair mc_pick_map_u16(int D, bool ahr, int path);
+KPair mc_pick_map_f32(int D, bool ahr, int path);

@@ -5,11 +5,30 @@
 #include "mc_kernels.h"
 #include "mc_launch.h"
 
+// Every kernel has a batched twin (suffix _b) that serves one pass of many
+// volumes of the same class: it finds its volume and unit in the launch's
+// index table and runs the very same unit function.
+__device__ __forceinline__ const McVol &mc_resolve(const McBatchSrc &s, uint32_t &u)
+{
+    const uint32_t r = blockIdx.x;
+    const uint32_t j = mc_batch_volume(s.pre, s.n, r);
+    u = r - s.pre[j];
+    return s.vols[s.list[j]];
+}
+
 template <typename Tin>
 __global__ __launch_bounds__(MC_T) void k_range_ghr(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
     mc::range_ghr_unit<Tin>(d, blockIdx.x, smem);
+}
+template <typename Tin>
+__global__ __launch_bounds__(MC_T) void k_range_ghr_b(McBatchSrc s)
+{
+    extern __shared__ __align__(16) char smem[];
+    uint32_t u;
+    const McVol &d = mc_resolve(s, u);
+    mc::range_ghr_unit<Tin>(d, u, smem);
 }
 
 template <typename Tin, bool AHR, bool RO, int PEEL>
@@ -18,12 +37,28 @@ __global__ __launch_bounds__(MC_T) void k_hist(McVol d)
     extern __shared__ __align__(16) char smem[];
     mc::hist_unit_dispatch<Tin, AHR, RO, PEEL>(d, blockIdx.x, smem);
 }
+template <typename Tin, bool AHR, bool RO, int PEEL>
+__global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s)
+{
+    extern __shared__ __align__(16) char smem[];
+    uint32_t u;
+    const McVol &d = mc_resolve(s, u);
+    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL>(d, u, smem);
+}
 
 template <typename Tin, int D, bool AHR>
 __global__ __launch_bounds__(MC_T) void k_map(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
     mc::map_unit<Tin, D, AHR>(d, blockIdx.x, smem);
+}
+template <typename Tin, int D, bool AHR>
+__global__ __launch_bounds__(MC_T) void k_map_b(McBatchSrc s)
+{
+    extern __shared__ __align__(16) char smem[];
+    uint32_t u;
+    const McVol &d = mc_resolve(s, u);
+    mc::map_unit<Tin, D, AHR>(d, u, smem);
 }
 
 template <typename Tin, bool AHR>
@@ -32,33 +67,46 @@ __global__ __launch_bounds__(MC_T) void k_map_generic(McVol d)
     extern __shared__ __align__(16) char smem[];
     mc::map_unit_generic<Tin, AHR>(d, blockIdx.x, smem);
 }
-
-
-template <typename Tin>
-static KFn pick_hist_t(bool ahr, bool ro, int peel)
+template <typename Tin, bool AHR>
+__global__ __launch_bounds__(MC_T) void k_map_generic_b(McBatchSrc s)
 {
-    if (ro) return (KFn)k_hist<Tin, true, true, 0>;
-    if (ahr) return peel == 0 ? (KFn)k_hist<Tin, true, false, 0>
-                  : peel == 1 ? (KFn)k_hist<Tin, true, false, 1> : (KFn)k_hist<Tin, true, false, 2>;
-    return peel == 0 ? (KFn)k_hist<Tin, false, false, 0>
-         : peel == 1 ? (KFn)k_hist<Tin, false, false, 1> : (KFn)k_hist<Tin, false, false, 2>;
+    extern __shared__ __align__(16) char smem[];
+    uint32_t u;
+    const McVol &d = mc_resolve(s, u);
+    mc::map_unit_generic<Tin, AHR>(d, u, smem);
 }
 
-template <typename Tin, bool AHR>
-static KFn pick_map_t(int D, int path)
+
+template <typename Tin, bool AHR, bool RO, int PEEL>
+static KPair hist_pair() { return KPair{(KFn)k_hist<Tin, AHR, RO, PEEL>, (KFnB)k_hist_b<Tin, AHR, RO, PEEL>}; }
+
+template <typename Tin>
+static KPair pick_hist_t(bool ahr, bool ro, int peel)
 {
-    if (path) return (KFn)k_map_generic<Tin, AHR>;
+    if (ro) return hist_pair<Tin, true, true, 0>();
+    if (ahr) return peel == 0 ? hist_pair<Tin, true, false, 0>()
+                  : peel == 1 ? hist_pair<Tin, true, false, 1>() : hist_pair<Tin, true, false, 2>();
+    return peel == 0 ? hist_pair<Tin, false, false, 0>()
+         : peel == 1 ? hist_pair<Tin, false, false, 1>() : hist_pair<Tin, false, false, 2>();
+}
+
+template <typename Tin, int D, bool AHR>
+static KPair map_pair() { return KPair{(KFn)k_map<Tin, D, AHR>, (KFnB)k_map_b<Tin, D, AHR>}; }
+
+template <typename Tin, bool AHR>
+static KPair pick_map_t(int D, int path)
+{
+    if (path) return KPair{(KFn)k_map_generic<Tin, AHR>, (KFnB)k_map_generic_b<Tin, AHR>};
     switch (D) {
-    case 1: return (KFn)k_map<Tin, 1, AHR>;
-    case 2: return (KFn)k_map<Tin, 2, AHR>;
-    case 3: return (KFn)k_map<Tin, 3, AHR>;
-    default: return (KFn)k_map<Tin, 4, AHR>;
+    case 1: return map_pair<Tin, 1, AHR>();
+    case 2: return map_pair<Tin, 2, AHR>();
+    case 3: return map_pair<Tin, 3, AHR>();
+    default: return map_pair<Tin, 4, AHR>();
     }
 }
 
 template <typename Tin>
-static KFn pick_map_t2(int D, bool ahr, int path)
+static KPair pick_map_t2(int D, bool ahr, int path)
 {
     return ahr ? pick_map_t<Tin, true>(D, path) : pick_map_t<Tin, false>(D, path);
 }
-

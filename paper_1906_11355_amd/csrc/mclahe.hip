@@ -2,10 +2,10 @@
 //
 // mclahe_run        : four stream-ordered launches (range, histogram,
 //                     clip/CDF/LUT, interpolation), one work-group per unit.
-// mclahe_run_batched: one persistent kernel that pulls the units of many
-//                     volumes from a phase-ordered ticket queue, replayed from
-//                     a cached hipGraph (descriptor copy, counter reset,
-//                     persistent launch).
+// mclahe_run_batched: the same four passes for a whole batch of volumes,
+//                     one launch per pass covering the units of every volume,
+//                     replayed from a cached hipGraph after one copy of the
+//                     batch's descriptor table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -86,7 +86,7 @@ static size_t map_lut_bytes(const mclahe_plan_s *p, int mG)
 {
     const int D = p->D;
     if (p->mode == MC_AHR) return (size_t)(1 << D) * p->nb * 4;
-    return (size_t)p->nb * (mG + 1) * (1 << (D - 1)) * 4;
+    return (size_t)p->nb * mc_lut_stride(mG + 1, 1 << (D - 1)) * 4;
 }
 
 // Extent of the last-axis hist segment made of kernels [kA,kB).
@@ -134,7 +134,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     const mclahe_tuning &t = p->tune;
 
     // ---- histogram units --------------------------------------------------
-    int R = t.hist_copies > 0 ? t.hist_copies : 2;
+    int R = t.hist_copies > 0 ? t.hist_copies : 2;   // 2 replicas: fastest on Poisson count data
     if (R != 1 && R != 2 && R != 4 && R != 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "hist_copies must be 1, 2, 4 or 8");
     const size_t hdr = hist_lds_header();
     while (R > 1 && hdr + (size_t)p->nb * R * 4 > MC_LDS_BUDGET) R /= 2;
@@ -182,8 +182,8 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.hP = P;
     v.hS = P == 1 ? (al.n + G - 1) / G : al.n * P;
     v.hR = R;
-    // hist_peel: 0 = default (one round), k >= 1 = k - 1 rounds
-    v.hPeel = t.hist_peel > 0 ? std::min(t.hist_peel - 1, 2) : 1;
+    // hist_peel: 0 = default (no aggregation), k >= 1 = k - 1 rounds
+    v.hPeel = t.hist_peel > 0 ? std::min(t.hist_peel - 1, 2) : 0;
     v.hCols = 1;
     int64_t omax_h = 1, rmax_h = 1;
     for (int i = 0; i < D - 1; ++i) {
@@ -220,7 +220,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     const int ncl = al.n - 1;  // cells on the last axis
     int mG = 1;
     if (fast && p->mode == MC_GHR) {
-        int want = t.map_group > 0 ? t.map_group : ncl;
+        int want = t.map_group > 0 ? t.map_group : ncl;   // default: largest that fits
         want = std::min(want, ncl);
         for (int g = want; g >= 1; --g) {
             if (otab + map_lut_bytes(p, g) > MC_LDS_BUDGET) continue;
@@ -319,29 +319,49 @@ static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, ch
     (void)es_in;
 }
 
-// Kernel selection lives in the per-dtype translation units (k_plain_*.hip)
-// and the persistent kernel in k_persist.hip.
+// Kernel selection lives in the per-dtype translation units (k_plain_*.hip).
 #include "mc_launch.h"
+#include "mc_plain_kernels.h"
 
 __global__ __launch_bounds__(MC_T) void k_clip(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
     mc::clip_unit(d, blockIdx.x, smem);
 }
+__global__ __launch_bounds__(MC_T) void k_clip_b(McBatchSrc s)
+{
+    extern __shared__ __align__(16) char smem[];
+    uint32_t u;
+    const McVol &d = mc_resolve(s, u);
+    mc::clip_unit(d, u, smem);
+}
 
-static KFn pick_range(int dt)
+// Kernel pair (per-volume, batched) of pass ph of a plan, and its LDS bytes.
+static KPair phase_kernels(const mclahe_plan_s *p, const McVol &v, int ph, size_t &lds)
 {
-    return dt == MC_U8 ? mc_pick_range_u8() : dt == MC_U16 ? mc_pick_range_u16() : mc_pick_range_f32();
-}
-static KFn pick_hist(int dt, bool ahr, bool ro, int peel)
-{
-    return dt == MC_U8 ? mc_pick_hist_u8(ahr, ro, peel)
-         : dt == MC_U16 ? mc_pick_hist_u16(ahr, ro, peel) : mc_pick_hist_f32(ahr, ro, peel);
-}
-static KFn pick_map(int dt, int D, bool ahr, int path)
-{
-    return dt == MC_U8 ? mc_pick_map_u8(D, ahr, path)
-         : dt == MC_U16 ? mc_pick_map_u16(D, ahr, path) : mc_pick_map_f32(D, ahr, path);
+    const int dt = p->in_dt;
+    const bool ahr = p->mode == MC_AHR;
+    switch (ph) {
+    case 0:
+        if (ahr) {
+            lds = p->lds_hist;
+            return dt == MC_U8 ? mc_pick_hist_u8(true, true, 0)
+                 : dt == MC_U16 ? mc_pick_hist_u16(true, true, 0) : mc_pick_hist_f32(true, true, 0);
+        }
+        lds = p->lds_range;
+        return dt == MC_U8 ? mc_pick_range_u8() : dt == MC_U16 ? mc_pick_range_u16() : mc_pick_range_f32();
+    case 1:
+        lds = p->lds_hist;
+        return dt == MC_U8 ? mc_pick_hist_u8(ahr, false, v.hPeel)
+             : dt == MC_U16 ? mc_pick_hist_u16(ahr, false, v.hPeel) : mc_pick_hist_f32(ahr, false, v.hPeel);
+    case 2:
+        lds = p->lds_clip;
+        return KPair{(KFn)k_clip, (KFnB)k_clip_b};
+    default:
+        lds = p->lds_map;
+        return dt == MC_U8 ? mc_pick_map_u8(p->D, ahr, v.path)
+             : dt == MC_U16 ? mc_pick_map_u16(p->D, ahr, v.path) : mc_pick_map_f32(p->D, ahr, v.path);
+    }
 }
 
 static mclahe_status launch(KFn f, uint32_t grid, size_t lds, hipStream_t st, const McVol &v)
@@ -355,23 +375,14 @@ static mclahe_status launch(KFn f, uint32_t grid, size_t lds, hipStream_t st, co
 static mclahe_status run_plain(const mclahe_plan_s *p, const McVol &v, hipStream_t st,
                                hipEvent_t *ev = nullptr)
 {
-    const bool ahr = p->mode == MC_AHR;
     mclahe_status s;
-    if (ev) HIPCHK(hipEventRecord(ev[0], st));
-    if (!ahr) {
-        if ((s = launch(pick_range(p->in_dt), v.n_range_wu, p->lds_range, st, v))) return s;
-    } else {
-        if ((s = launch(pick_hist(p->in_dt, true, true, 0), v.n_hist_wu, p->lds_hist, st, v)))
-            return s;
+    for (int ph = 0; ph < MC_PHASES; ++ph) {
+        if (ev) HIPCHK(hipEventRecord(ev[ph], st));
+        size_t lds = 0;
+        const KPair k = phase_kernels(p, v, ph, lds);
+        if ((s = launch(k.plain, mc_phase_units(v, ph), lds, st, v))) return s;
     }
-    if (ev) HIPCHK(hipEventRecord(ev[1], st));
-    if ((s = launch(pick_hist(p->in_dt, ahr, false, v.hPeel), v.n_hist_wu, p->lds_hist, st, v)))
-        return s;
-    if (ev) HIPCHK(hipEventRecord(ev[2], st));
-    if ((s = launch((KFn)k_clip, v.n_clip_wu, p->lds_clip, st, v))) return s;
-    if (ev) HIPCHK(hipEventRecord(ev[3], st));
-    if ((s = launch(pick_map(p->in_dt, p->D, ahr, v.path), v.n_map_wu, p->lds_map, st, v))) return s;
-    if (ev) HIPCHK(hipEventRecord(ev[4], st));
+    if (ev) HIPCHK(hipEventRecord(ev[MC_PHASES], st));
     return MCLAHE_SUCCESS;
 }
 
@@ -380,77 +391,107 @@ struct mclahe_timer_s {
     int max_runs = 0, runs = 0;
 };
 
-// Batched workspace: [queue header | done counters | batch header | vstart |
-// volume table | per-volume workspaces...]
-struct BatchLayout {
-    uint64_t o_queue, o_done, o_hdr, o_vstart, o_vols, o_first, total;
-    std::vector<uint64_t> vol_off;
+// Batched workspace: [descriptor table | per-volume workspaces...].  The
+// table (header, launch records, index arrays, volume descriptors) is written
+// by one stream-ordered copy per call; the per-volume workspaces are laid out
+// as for mclahe_run.  Launch grouping depends only on the plans.
+struct BatchLaunch {
+    int phase;
+    KFnB fn;
     size_t lds;
+    std::vector<uint32_t> vols;   // volume indices
+    std::vector<uint32_t> pre;    // unit prefix sums
+};
+
+struct BatchLayout {
+    uint64_t o_table, o_recs, o_idx, o_vols, o_first, total;
+    std::vector<uint64_t> vol_off;
+    std::vector<BatchLaunch> launches;
+    uint32_t n_idx = 0;
 };
 
 static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout &L)
 {
     if (n < 1 || !plans) return fail(MCLAHE_ERROR_INVALID_VALUE, "batched call needs n >= 1 plans");
+    for (int i = 0; i < n; ++i)
+        if (!plans[i]) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan %d is NULL", i);
+    // group the volumes of each pass by kernel class
+    L.launches.clear();
+    for (int ph = 0; ph < MC_PHASES; ++ph) {
+        const size_t first = L.launches.size();
+        for (int i = 0; i < n; ++i) {
+            const mclahe_plan_s *p = plans[i];
+            const uint32_t units = mc_phase_units(p->v, ph);
+            if (!units) continue;
+            size_t lds = 0;
+            const KPair k = phase_kernels(p, p->v, ph, lds);
+            BatchLaunch *bl = nullptr;
+            for (size_t j = first; j < L.launches.size(); ++j)
+                if (L.launches[j].fn == k.batch) bl = &L.launches[j];
+            if (!bl) {
+                L.launches.push_back(BatchLaunch{ph, k.batch, 0, {}, {0}});
+                bl = &L.launches.back();
+            }
+            bl->lds = std::max(bl->lds, lds);
+            bl->vols.push_back((uint32_t)i);
+            bl->pre.push_back(bl->pre.back() + units);
+        }
+    }
+    L.n_idx = 0;
+    for (auto &bl : L.launches) L.n_idx += (uint32_t)(bl.vols.size() + bl.pre.size());
     uint64_t o = 0;
-    L.o_queue = o;
-    o = align256(o + sizeof(McQueue));
-    L.o_done = o;
-    o = align256(o + (uint64_t)MC_PHASES * n * 4);
-    L.o_hdr = o;
-    o = align256(o + sizeof(McBatch));
-    L.o_vstart = o;
-    o = align256(o + (uint64_t)MC_PHASES * (n + 1) * 4);
+    L.o_table = o;
+    o = align256(o + sizeof(McBatchHdr));
+    L.o_recs = o;
+    o = align256(o + L.launches.size() * sizeof(McLaunchRec));
+    L.o_idx = o;
+    o = align256(o + (uint64_t)L.n_idx * 4);
     L.o_vols = o;
     o = align256(o + (uint64_t)n * sizeof(McVol));
     L.o_first = o;
     L.vol_off.resize(n);
-    L.lds = 2 * MC_T * 8;
     for (int i = 0; i < n; ++i) {
-        if (!plans[i]) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan %d is NULL", i);
         L.vol_off[i] = o;
         o = align256(o + plans[i]->total);
-        const mclahe_plan_s *p = plans[i];
-        L.lds = std::max({L.lds, p->lds_range, p->lds_hist, p->lds_clip, p->lds_map});
     }
     L.total = o;
     return MCLAHE_SUCCESS;
 }
 
-// Host image of the table region [o_hdr, o_first).
+// Host image of the table region [o_table, o_first).
 static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins, void *const *outs,
                        char *ws, const BatchLayout &L, std::vector<char> &img)
 {
-    img.assign(L.o_first - L.o_hdr, 0);
-    McBatch *h = (McBatch *)img.data();
-    uint32_t *vs = (uint32_t *)(img.data() + (L.o_vstart - L.o_hdr));
-    McVol *vols = (McVol *)(img.data() + (L.o_vols - L.o_hdr));
+    img.assign(L.o_first - L.o_table, 0);
+    McBatchHdr *h = (McBatchHdr *)img.data();
+    McLaunchRec *recs = (McLaunchRec *)(img.data() + L.o_recs);
+    uint32_t *idx = (uint32_t *)(img.data() + L.o_idx);
+    McVol *vols = (McVol *)(img.data() + L.o_vols);
     for (int i = 0; i < n; ++i) bind(plans[i], vols[i], ins[i], outs[i], ws + L.vol_off[i]);
     h->nvol = (uint32_t)n;
-    uint32_t acc = 0;
-    for (int ph = 0; ph < MC_PHASES; ++ph) {
-        h->phase_start[ph] = acc;
-        uint32_t in_ph = 0;
-        for (int i = 0; i < n; ++i) {
-            vs[ph * (n + 1) + i] = in_ph;
-            const McVol &v = vols[i];
-            const uint32_t c = ph == 0 ? (v.mode == MC_AHR ? v.n_hist_wu : v.n_range_wu)
-                             : ph == 1 ? v.n_hist_wu : ph == 2 ? v.n_clip_wu : v.n_map_wu;
-            in_ph += c;
-        }
-        vs[ph * (n + 1) + n] = in_ph;
-        acc += in_ph;
+    h->nlaunch = (uint32_t)L.launches.size();
+    uint32_t k = 0;
+    for (size_t j = 0; j < L.launches.size(); ++j) {
+        const BatchLaunch &bl = L.launches[j];
+        McLaunchRec &r = recs[j];
+        r.phase = (uint32_t)bl.phase;
+        r.n = (uint32_t)bl.vols.size();
+        r.list = k;
+        for (uint32_t v : bl.vols) idx[k++] = v;
+        r.pre = k;
+        for (uint32_t u : bl.pre) idx[k++] = u;
+        r.units = bl.pre.back();
     }
-    h->phase_start[MC_PHASES] = acc;
-    h->total = acc;
-    h->spin_limit = 1u << 24;
 }
 
+// A cached graph of the batched launches for one batch signature (plans and
+// workspace address), with a ring of pinned host images of the descriptor
+// table (a slot is reused only after the copy that read it has run).
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr;
-    std::vector<char *> host;     // pinned descriptor images (ring)
-    std::vector<hipEvent_t> ev;   // completion of the launch that used a slot
+    std::vector<char *> host;
+    std::vector<hipEvent_t> ev;
     std::vector<bool> used;
     int next = 0;
     size_t bytes = 0;
@@ -459,53 +500,43 @@ struct GraphEntry {
 static std::mutex g_graph_mu;
 static std::map<std::string, GraphEntry *> g_graphs;
 
-static int persistent_grid(size_t lds, int want)
-{
-    if (want > 0) return want;
-    int dev = 0, ncu = MC_NUM_CU, occ = 1;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-    }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, mc_persistent_fn(), MC_T, lds) != hipSuccess || occ < 1)
-        occ = 1;
-    return ncu * occ;
-}
-
-static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, char *ws, int grid)
+// Graph: the launches of one pass are independent branches; every launch of
+// pass ph depends on every launch of the previous non-empty pass.
+static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std::vector<char> &img, char *ws)
 {
     HIPCHK(hipGraphCreate(&g->graph, 0));
-    // 1. descriptor table copy (host image of the current call)
-    HIPCHK(hipGraphAddMemcpyNode1D(&g->copy, g->graph, nullptr, 0, ws + L.o_hdr, g->host[0], g->bytes,
-                                   hipMemcpyHostToDevice));
-    // 2. reset of the queue head, error word and completion counters
-    hipGraphNode_t zero;
-    hipKernelNodeParams zp = {};
-    uint32_t *zptr = (uint32_t *)(ws + L.o_queue);
-    uint32_t zn = (uint32_t)((L.o_hdr - L.o_queue) / 4);
-    void *zargs[] = {&zptr, &zn};
-    zp.func = (void *)mc_zero_fn();
-    zp.gridDim = dim3(std::max<uint32_t>(1, std::min<uint32_t>(64, (zn + 255) / 256)));
-    zp.blockDim = dim3(256);
-    zp.sharedMemBytes = 0;
-    zp.kernelParams = zargs;
-    HIPCHK(hipGraphAddKernelNode(&zero, g->graph, nullptr, 0, &zp));
-    // 3. the persistent kernel
-    hipGraphNode_t pers;
-    hipKernelNodeParams pp = {};
-    const McBatch *hdr = (const McBatch *)(ws + L.o_hdr);
-    const uint32_t *vstart = (const uint32_t *)(ws + L.o_vstart);
-    const McVol *vols = (const McVol *)(ws + L.o_vols);
-    McQueue *q = (McQueue *)(ws + L.o_queue);
-    uint32_t *done = (uint32_t *)(ws + L.o_done);
-    void *pargs[] = {&hdr, &vstart, &vols, &q, &done};
-    pp.func = (void *)mc_persistent_fn();
-    pp.gridDim = dim3(grid);
-    pp.blockDim = dim3(MC_T);
-    pp.sharedMemBytes = (unsigned)L.lds;
-    pp.kernelParams = pargs;
-    hipGraphNode_t deps[2] = {g->copy, zero};
-    HIPCHK(hipGraphAddKernelNode(&pers, g->graph, deps, 2, &pp));
+    const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
+    const uint32_t *idx_dev = (const uint32_t *)(ws + L.o_table + L.o_idx);
+    const McVol *vols_dev = (const McVol *)(ws + L.o_table + L.o_vols);
+    std::vector<hipGraphNode_t> prev, cur;
+    int cur_phase = -1;
+    for (size_t j = 0; j < L.launches.size(); ++j) {
+        const BatchLaunch &bl = L.launches[j];
+        if (bl.phase != cur_phase) {
+            if (!cur.empty()) prev = cur;
+            cur.clear();
+            cur_phase = bl.phase;
+        }
+        if (bl.lds > 64 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void *)bl.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bl.lds));
+        McBatchSrc src;
+        src.vols = vols_dev;
+        src.list = idx_dev + recs[j].list;
+        src.pre = idx_dev + recs[j].pre;
+        src.n = recs[j].n;
+        src.pad_ = 0;
+        void *args[] = {&src};
+        hipKernelNodeParams kp = {};
+        kp.func = (void *)bl.fn;
+        kp.gridDim = dim3(recs[j].units);
+        kp.blockDim = dim3(MC_T);
+        kp.sharedMemBytes = (unsigned)bl.lds;
+        kp.kernelParams = args;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, g->graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
+        cur.push_back(node);
+    }
     HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     return MCLAHE_SUCCESS;
 }
@@ -535,7 +566,7 @@ static void tune_cache_load()
     char key[512];
     mclahe_tuning t;
     while (fscanf(fp, "%511s %d %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
-                  &t.map_rows_split, &t.map_group, &t.persistent_blocks) == 7)
+                  &t.map_rows_split, &t.map_group, &t.reserved) == 7)
         g_tune_cache[key] = t;
     fclose(fp);
 }
@@ -548,7 +579,7 @@ static void tune_cache_store(const std::string &key, const mclahe_tuning &t)
     FILE *fp = fopen(f, "a");
     if (!fp) return;
     fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
-            t.map_rows_split, t.map_group, t.persistent_blocks);
+            t.map_rows_split, t.map_group, t.reserved);
     fclose(fp);
 }
 
@@ -724,7 +755,7 @@ mclahe_status mclahe_plan_get_tuning(mclahe_plan_t p, mclahe_tuning *t)
     t->hist_peel = p->v.hPeel + 1;
     t->map_rows_split = p->v.mCr;
     t->map_group = p->v.mG;
-    t->persistent_blocks = p->tune.persistent_blocks;
+    t->reserved = p->tune.reserved;
     return MCLAHE_SUCCESS;
 }
 
@@ -732,7 +763,7 @@ mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
 {
     if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
     if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->hist_peel < 0 ||
-        t->hist_peel > 3 || t->persistent_blocks < 0 || t->hist_copies < 0)
+        t->hist_peel > 3 || t->reserved < 0 || t->hist_copies < 0)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "tuning fields must be >= 0 (hist_peel <= 3)");
     const mclahe_tuning old = p->tune;
     p->tune = *t;
@@ -877,6 +908,22 @@ mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans
     return MCLAHE_SUCCESS;
 }
 
+mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                   void *const *d_out, void *d_ws, void *host_image, size_t image_bytes,
+                                   size_t *needed)
+{
+    g_err.clear();
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    if (!d_in || !d_out || !needed) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    std::vector<char> img;
+    fill_table(n, plans, d_in, d_out, (char *)d_ws, L, img);
+    *needed = img.size();
+    if (host_image) memcpy(host_image, img.data(), std::min(image_bytes, img.size()));
+    return MCLAHE_SUCCESS;
+}
+
 mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *const *d_in,
                                  void *const *d_out, void *d_ws, size_t wsb, void *stream)
 {
@@ -890,16 +937,11 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
         if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
     }
     char *ws = (char *)d_ws;
+    hipStream_t st = (hipStream_t)stream;
     std::vector<char> img;
     fill_table(n, plans, d_in, d_out, ws, L, img);
-    int want = 0;
-    for (int i = 0; i < n; ++i) want = std::max(want, plans[i]->tune.persistent_blocks);
-    const int grid = persistent_grid(L.lds, want);
-    if (L.lds > 64 * 1024)
-        HIPCHK(hipFuncSetAttribute(mc_persistent_fn(), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)L.lds));
 
-    std::string key = std::to_string((uintptr_t)ws) + ":" + std::to_string(grid) + ":" + std::to_string(n);
+    std::string key = std::to_string((uintptr_t)ws) + ":" + std::to_string(n);
     for (int i = 0; i < n; ++i) key += ":" + std::to_string((uintptr_t)plans[i]) + "/" + plan_key(plans[i]);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     GraphEntry *g;
@@ -907,18 +949,16 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
     if (it == g_graphs.end()) {
         g = new GraphEntry();
         g->bytes = img.size();
-        const int ring = 4;
-        for (int r = 0; r < ring; ++r) {
-            char *h = nullptr;
-            HIPCHK(hipHostMalloc((void **)&h, g->bytes, hipHostMallocDefault));
-            g->host.push_back(h);
+        for (int r = 0; r < 4; ++r) {
+            char *hb = nullptr;
+            HIPCHK(hipHostMalloc((void **)&hb, g->bytes, hipHostMallocDefault));
+            g->host.push_back(hb);
             hipEvent_t e;
             HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             g->ev.push_back(e);
             g->used.push_back(false);
         }
-        memcpy(g->host[0], img.data(), g->bytes);
-        s = build_graph(g, L, ws, grid);
+        s = build_graph(g, L, img, ws);
         if (s) return s;
         g_graphs[key] = g;
     } else {
@@ -928,11 +968,10 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
     g->next = (g->next + 1) % (int)g->host.size();
     if (g->used[slot]) HIPCHK(hipEventSynchronize(g->ev[slot]));
     memcpy(g->host[slot], img.data(), g->bytes);
-    HIPCHK(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, ws + L.o_hdr, g->host[slot], g->bytes,
-                                             hipMemcpyHostToDevice));
-    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
-    HIPCHK(hipEventRecord(g->ev[slot], (hipStream_t)stream));
+    HIPCHK(hipMemcpyAsync(ws + L.o_table, g->host[slot], g->bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(g->ev[slot], st));
     g->used[slot] = true;
+    HIPCHK(hipGraphLaunch(g->exec, st));
     return MCLAHE_SUCCESS;
 }
 
