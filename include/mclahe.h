@@ -113,11 +113,12 @@ typedef struct {
  *                       2 = one round, 3 = two rounds (0 = default)
  *   map_rows_split    : row chunks per cell column in the interpolation pass
  *   map_group         : interpolation cells per work unit along the last axis
- *   reserved          : must be 0                                           */
+ *   hist_hotbin       : register cache of each wave's most frequent bin in the
+ *                       histogram pass: 1 = off, 2 = on (0 = default, off)  */
 typedef struct {
     int32_t hist_rows_split, hist_copies, hist_peel;
     int32_t map_rows_split, map_group;
-    int32_t reserved;
+    int32_t hist_hotbin;
 } mclahe_tuning;
 
 /* Create a plan (host only; no device call).  Arguments follow the paper's

@@ -13,7 +13,8 @@ from typing import Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmclahe.so")
+# MCLAHE_LIB may name another build of the same library (e.g. an installed one)
+LIB_PATH = os.environ.get("MCLAHE_LIB") or os.path.join(_HERE, "libmclahe.so")
 
 SUCCESS, INVALID_VALUE, NOT_SUPPORTED, OUT_OF_MEMORY, WORKSPACE, HIP_ERROR = range(6)
 U8, U16, F32 = 0, 1, 2
@@ -41,7 +42,7 @@ class Geometry(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("hist_rows_split", "hist_copies", "hist_peel",
-                                                "map_rows_split", "map_group", "reserved")]
+                                                "map_rows_split", "map_group", "hist_hotbin")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

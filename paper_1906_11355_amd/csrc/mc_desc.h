@@ -14,6 +14,10 @@
 
 #define MC_MAXD 8          // dimensions supported
 #define MC_T 256           // threads per work-group (4 wavefronts of 64)
+#define MC_MAP_T 512       // threads per work-group of the LDS-staged map with
+                           // a global range (its LDS bounds the units per CU:
+                           // bigger groups keep more waves in flight); the
+                           // adaptive-range map, heavier in registers, uses MC_T
 #define MC_OMAX 256        // outer-row table entries per work unit
 #define MC_LDS_BUDGET (64 * 1024)   // LDS a work unit may use (bytes)
 #define MC_NUM_CU 256      // MI355X compute units (tiling target)
@@ -97,6 +101,13 @@ MC_HD int32_t mc_lut_stride(int32_t nlk, int32_t NO)
     return q * cw;
 }
 
+// LDS words of one slot (kernel) of a histogram unit: n bins x R replicas,
+// plus one word so that the stride is odd and slots spread over the banks.
+MC_HD int32_t mc_hist_slot_stride(int32_t nb, int32_t R) { return nb * R + 1; }
+
+// Work-group size of the LDS-staged map kernels.
+MC_HD constexpr int mc_map_threads(bool ahr) { return ahr ? MC_T : MC_MAP_T; }
+
 // Everything the kernels need about one volume.
 struct McVol {
     // ---- problem -----------------------------------------------------------
@@ -113,6 +124,9 @@ struct McVol {
     int32_t hG, hP, hS, hCr;  // kernels per segment, parts per kernel,
                               // segments on the last axis, row chunks
     int32_t hR, hPeel;        // LDS replicas, aggregation rounds
+    int32_t hHot;             // register cache of each wave's most frequent bin
+    int32_t ntst;             // 1: output row segments are whole 64-byte blocks
+                              //    -> streaming (non-temporal) stores
     int64_t hCols;            // kernel columns (prod of n_i, i < D-1)
     uint32_t n_hist_wu;       // hCols * hS * hCr
     uint32_t n_range_wu;      // GHR min/max blocks (0 if a user range is given)

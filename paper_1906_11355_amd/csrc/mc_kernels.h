@@ -35,8 +35,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // by the oracle; scale = +inf for a degenerate range gives 0 / n-1 as well).
 __device__ __forceinline__ int bin_of(float v, float lo, float scale, float nbf, int nbm1)
 {
+    (void)nbf;
     const float t = (v - lo) * scale;
-    const int r = (t >= nbf) ? nbm1 : (int)t;
+    // t >= n-1 truncates to n-1 either way; fminf maps NaN to n-1, which the
+    // t > 0 test then sends to bin 0 as the reading requires
+    const int r = (int)fminf(t, (float)nbm1);
     return (t > 0.0f) ? r : 0;
 }
 
@@ -95,7 +98,7 @@ __device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
 __device__ __forceinline__ void store_elem(void *out, int dt, int64_t i, float y)
 {
     if (dt == MC_F32) {
-        __builtin_nontemporal_store(y, (float *)out + i);
+        ((float *)out)[i] = y;
     } else {
         const float M = dt == MC_U8 ? 255.0f : 65535.0f;
         float q = floorf(y * M + 0.5f);
@@ -171,15 +174,17 @@ __device__ __forceinline__ void rowspace_finish(const McVol &d, RowSpace &rs)
 
 // Decode o (flattened axes 0..D-3) into coordinates; unrolled with guards so
 // that every array index is a compile-time constant (no scratch memory).
-__device__ __forceinline__ void decode_outer(const McVol &d, const RowSpace &rs, int64_t o,
+__device__ __forceinline__ void decode_outer(const McVol &d, const RowSpace &rs, int64_t o64,
                                              int32_t (&x)[MC_MAXD])
 {
+    // o indexes the outer rows of one kernel or cell box: < 2^31
     const int D = d.D;
+    uint32_t o = (uint32_t)o64;
 #pragma unroll
     for (int i = MC_MAXD - 1; i >= 0; --i) {
         if (i <= D - 3) {
-            const int64_t q = o / rs.len[i];
-            x[i] = rs.lo[i] + (int32_t)(o - q * rs.len[i]);
+            const uint32_t q = o / (uint32_t)rs.len[i];
+            x[i] = rs.lo[i] + (int32_t)(o - q * (uint32_t)rs.len[i]);
             o = q;
         }
     }
@@ -433,7 +438,7 @@ __device__ __forceinline__ HistLds hist_lds(const McVol &d, char *smem)
 // Wavefront-aggregated LDS histogram update: lanes whose key equals the
 // first active lane's key add their summed weight with one atomic.
 template <int PEEL>
-__device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int R, int cp)
+__device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int cp)
 {
     if constexpr (PEEL > 0) {
         unsigned long long act = __ballot(key >= 0);
@@ -457,12 +462,12 @@ __device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int
                 for (int b = 0; b < 9; ++b)
                     sum += (uint32_t)__popcll(__ballot(same && ((val >> b) & 1u))) << b;
             }
-            if (lane_id() == leader) atomicAdd(&h[lkey * R + cp], sum);
+            if (lane_id() == leader) atomicAdd(&h[lkey + cp], sum);
             if (same) key = -1;
             act &= ~sm;
         }
     }
-    if (key >= 0) atomicAdd(&h[key * R + cp], val);
+    if (key >= 0) atomicAdd(&h[key + cp], val);
 }
 
 template <typename Tin, int V, bool AHR, bool RANGE_ONLY, int PEEL>
@@ -479,6 +484,9 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     hist_segment(d, seg, kA, kB, xs, xe);
     const int nslot = kB - kA;
     const int R = RANGE_ONLY ? 1 : d.hR;
+    // LDS words per slot: n*R + 1, odd, so that one bin of different slots
+    // (kernels of the segment) falls in different banks
+    const int SS = mc_hist_slot_stride(nb, R);
 
     // rows of this chunk
     const int64_t r0 = rs.rows * chunk / d.hCr, r1 = rs.rows * (chunk + 1) / d.hCr;
@@ -525,7 +533,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                 }
             }
         }
-        const int hsz = nslot * nb * R;
+        const int hsz = nslot * SS;
         for (int i = threadIdx.x; i < hsz; i += MC_T) L.h[i] = 0;
     } else {
         for (int i = threadIdx.x; i < 2 * nslot; i += MC_T)
@@ -559,6 +567,14 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     }
     const int cp = R > 1 ? (lane_id() & (R - 1)) : 0;
     const Tin *in = (const Tin *)d.in;
+    // Register cache of the wave's most frequent bin: hits on it are summed
+    // in registers and added to LDS once at the end, so the lanes that would
+    // all hit one LDS address (a dominant background value) issue no atomics.
+    // Integer sums: the histogram is unchanged, bit for bit.
+    int hot = -1;
+    uint32_t hc[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) hc[e] = 0;
 
     if (tact) {
         const int64_t rstart = r0 + trow;
@@ -597,6 +613,27 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
             if (!ok[u]) break;
             const float (&f)[V] = fu[u];
             const uint32_t wrow = wrs[u];
+            if constexpr (!RANGE_ONLY) {
+                if (d.hHot && row == rstart && u == 0) {
+                    // the wave's most frequent bin among its lanes' first
+                    // values (ballots count active lanes only)
+                    const int b0 = m.s1[0] >= 0 ? bin_of(f[0], lo1[0], sc1[0], nbf, nbm1) : -1;
+                    unsigned long long act = __ballot(b0 >= 0);
+                    int best = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        if (!act) break;
+                        const int cand = __shfl(b0, __ffsll((long long)act) - 1);
+                        const unsigned long long sm = __ballot(b0 == cand);
+                        const int cnt = __popcll(sm);
+                        if (cnt > best) {
+                            best = cnt;
+                            hot = cand;
+                        }
+                        act &= ~sm;
+                    }
+                }
+            }
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 if constexpr (RANGE_ONLY) {
@@ -612,10 +649,13 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                         }
                     }
                 } else {
-                    int key = -1;
-                    if (m.s1[e] >= 0)
-                        key = m.s1[e] * nb + bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
-                    hist_add<PEEL>(L.h, key, wrow * m.w1[e], R, cp);
+                    int key = -1;      // LDS word of (slot, bin), replica 0
+                    if (m.s1[e] >= 0) {
+                        const int b = bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
+                        if (b == hot) hc[e] += wrow * m.w1[e];
+                        else key = m.s1[e] * SS + b * R;
+                    }
+                    hist_add<PEEL>(L.h, key, wrow * m.w1[e], cp);
                     if (m.extra[e]) {
                         uint32_t ex = m.extra[e];
                         while (ex) {
@@ -623,8 +663,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                             const uint32_t w = (ex >> 8) & 0xff;
                             const float lo = AHR ? L.slot_lo[s] : glo;
                             const float sc = AHR ? L.slot_sc[s] : gsc;
-                            atomicAdd(&L.h[(s * nb + bin_of(f[e], lo, sc, nbf, nbm1)) * R + cp],
-                                      wrow * w);
+                            atomicAdd(&L.h[s * SS + bin_of(f[e], lo, sc, nbf, nbm1) * R + cp], wrow * w);
                             ex >>= 16;
                         }
                     }
@@ -641,6 +680,10 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                 atomicMax(&L.slot_mm[2 * m.s1[e] + 1], f2o(mx[e]));
             }
         }
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (hc[e]) atomicAdd(&L.h[m.s1[e] * SS + hot * R + cp], hc[e]);
     }
     __syncthreads();
     if constexpr (RANGE_ONLY) {
@@ -659,8 +702,10 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int tot = d.hG * nb;
         for (int i = threadIdx.x; i < tot; i += MC_T) {
             uint32_t s = 0;
-            if (i < nslot * nb)
-                for (int c = 0; c < R; ++c) s += L.h[i * R + c];
+            if (i < nslot * nb) {
+                const int sl = i / nb, b = i - sl * nb;
+                for (int c = 0; c < R; ++c) s += L.h[sl * SS + b * R + c];
+            }
             dst[i] = s;
         }
     }
@@ -731,13 +776,31 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
 }
 
 // ------------------------------------------------------------------- map --
-// Interpolation units: a cell column (one cell per outer axis) x a group of
-// cells on the last axis x a chunk of rows.  The LUTs of the 2^(D-1) outer
+// Interpolation units (MC_MAP_T threads): a cell column (one cell per outer
+// axis) x a group of cells on the last axis x a chunk of rows.  The LUTs of the 2^(D-1) outer
 // corner kernels times the group's last-axis kernels are staged in LDS.
+// Work-groups are dispatched to the 8 XCDs of the chip round-robin, and each
+// XCD has its own L2.  The mS units that share the same rows (one per
+// last-axis group) read the same cache lines, so they are ordered to run
+// back to back on one XCD: unit index u on XCD u % 8 takes the k-th unit of
+// that XCD, k = u / 8, as group k % mS of row set (k / mS) * 8 + u % 8.
+// Only the order changes, never what a unit computes.
+__device__ __forceinline__ uint32_t map_unit_order(const McVol &d, uint32_t u)
+{
+    const uint32_t ns = (uint32_t)d.mS;
+    const uint32_t ncc = d.n_map_wu / ns;           // (cell column, chunk) pairs
+    if (ns == 1 || (ncc & 7u)) return u;
+    const uint32_t x = u & 7u, k = u >> 3;
+    const uint32_t g = k % ns, cc = (k / ns) * 8u + x;
+    const uint32_t col = cc / (uint32_t)d.mCr, chunk = cc - col * (uint32_t)d.mCr;
+    return (col * ns + g) * (uint32_t)d.mCr + chunk;
+}
+
 __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int &chunk, int &grp,
                                                 int32_t (&cidx)[MC_MAXD], RowSpace &rs)
 {
     const int D = d.D;
+    wu = map_unit_order(d, wu);
     chunk = (int)(wu % (uint32_t)d.mCr);
     const uint32_t t1 = wu / (uint32_t)d.mCr;
     grp = (int)(t1 % (uint32_t)d.mS);
@@ -777,6 +840,7 @@ struct MapOTab {
 template <typename Tin, int D, bool AHR, int V>
 __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
 {
+    constexpr int NT = mc_map_threads(AHR);   // work-group size
     constexpr int NC = 1 << D;                 // corners
     constexpr int NO = 1 << (D - 1);           // outer corners
     using OT = MapOTab<D>;
@@ -826,18 +890,18 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     // different bins spread over the banks.  AHR: [lk*NO + corner'][bin].
     const int nlk = ncl + 1;
     const int SB = AHR ? 0 : mc_lut_stride(nlk, NO);
-    const int tot = nb * nlk * NO;
-    for (int i = threadIdx.x; i < tot; i += MC_T) {
-        const int b = i % nb;
-        const int t = i / nb;
-        const int co = t % NO, lk = t / NO;
+    for (int t = 0; t < nlk * NO; ++t) {          // one kernel's LUT per step
+        const int co = t % NO, lk = t / NO;       // NO is a power of two
         int64_t kid = kbase + cA + lk;
 #pragma unroll
         for (int j = 0; j < D - 1; ++j)
             if ((co >> (D - 2 - j)) & 1) kid += kst[j];
-        const float v = d.lut[kid * nb + b];
-        if constexpr (AHR) lut[i] = v;
-        else lut[b * SB + lk * NO + co] = v;
+        const float *src = d.lut + kid * nb;
+        if constexpr (AHR) {
+            for (int b = threadIdx.x; b < nb; b += NT) lut[t * nb + b] = src[b];
+        } else {
+            for (int b = threadIdx.x; b < nb; b += NT) lut[__umul24(b, SB) + lk * NO + co] = src[b];
+        }
     }
     // per-corner ranges (AHR: one last-axis cell per unit)
     float clo[NC], csc[NC];
@@ -864,7 +928,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int64_t r0 = rs.rows * chunk / d.mCr, r1 = rs.rows * (chunk + 1) / d.mCr;
     const int64_t o0 = r0 / rs.in_len;
     const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
-    for (int j = threadIdx.x; j < ocnt; j += MC_T) {
+    for (int j = threadIdx.x; j < ocnt; j += NT) {
         int32_t x[MC_MAXD];
         decode_outer(d, rs, o0 + j, x);
         int64_t off = 0;
@@ -896,7 +960,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     if (xe <= xs) return;
     const int c_lo = xs / V, c_hi = (xe + V - 1) / V;
     const int cpr = c_hi - c_lo;
-    const int rpi = MC_T / cpr;
+    const int rpi = NT / cpr;
     const int tch = threadIdx.x % cpr, trow = threadIdx.x / cpr;
     if (!(trow < rpi)) return;
     const int64_t xoff = (int64_t)(c_lo + tch) * V;
@@ -927,9 +991,9 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
     const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
-    // rows whose loads are in flight together; the staged LUTs bound this
-    // kernel's occupancy, so registers are spent on memory parallelism
-    constexpr int U = V >= 8 ? 4 : 8;
+    // rows whose loads are in flight together (with NT threads and two
+    // units per CU this keeps ~64 KiB of loads in flight per CU)
+    constexpr int U = V >= 8 ? 2 : 4;
     for (int64_t row = rstart; row < r1; row += (int64_t)U * rpi) {
         int64_t offs[U];
         float win[U];
@@ -978,10 +1042,10 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                 if constexpr (AHR) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c)
-                        Lv[c] = lut[c * nb + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
+                        Lv[c] = lut[__umul24(c, nb) + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
                 } else {
                     const int b = bin_of(fe, glo, gsc, nbf, nbm1);
-                    const float *p = lut + b * SB + lbase[e];
+                    const float *p = lut + __umul24(b, SB) + lbase[e];
                     if constexpr (NO % 4 == 0) {
 #pragma unroll
                         for (int c = 0; c < NC; c += 4) {
@@ -1013,12 +1077,20 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             }
             const int64_t off = offs[u];
             if (vecst) {
+                // streaming stores when the unit writes whole cache lines;
+                // otherwise write-back stores let L2 merge the parts of a
+                // line that neighbouring units write
                 if constexpr (V % 4 == 0) {
                     f4 *op = (f4 *)((float *)d.out + off);
+                    if (d.ntst) {
 #pragma unroll
-                    for (int q = 0; q < V / 4; ++q) {
-                        f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
-                        __builtin_nontemporal_store(t, op + q);
+                        for (int q = 0; q < V / 4; ++q) {
+                            f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                            __builtin_nontemporal_store(t, op + q);
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < V / 4; ++q) op[q] = f4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
                     }
                 }
             } else {

@@ -9,6 +9,7 @@ typedef void (*KFnB)(McBatchSrc);   // batched twin: many volumes of one class
 struct KPair {
     KFn plain;
     KFnB batch;
+    int threads;   // work-group size of both
 };
 
 KPair mc_pick_range_u8();

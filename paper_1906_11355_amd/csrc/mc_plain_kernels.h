@@ -47,13 +47,13 @@ __global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s)
 }
 
 template <typename Tin, int D, bool AHR>
-__global__ __launch_bounds__(MC_T) void k_map(McVol d)
+__global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
     mc::map_unit<Tin, D, AHR>(d, blockIdx.x, smem);
 }
 template <typename Tin, int D, bool AHR>
-__global__ __launch_bounds__(MC_T) void k_map_b(McBatchSrc s)
+__global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map_b(McBatchSrc s)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(MC_T) void k_map_generic_b(McBatchSrc s)
 
 
 template <typename Tin, bool AHR, bool RO, int PEEL>
-static KPair hist_pair() { return KPair{(KFn)k_hist<Tin, AHR, RO, PEEL>, (KFnB)k_hist_b<Tin, AHR, RO, PEEL>}; }
+static KPair hist_pair() { return KPair{(KFn)k_hist<Tin, AHR, RO, PEEL>, (KFnB)k_hist_b<Tin, AHR, RO, PEEL>, MC_T}; }
 
 template <typename Tin>
 static KPair pick_hist_t(bool ahr, bool ro, int peel)
@@ -91,12 +91,12 @@ static KPair pick_hist_t(bool ahr, bool ro, int peel)
 }
 
 template <typename Tin, int D, bool AHR>
-static KPair map_pair() { return KPair{(KFn)k_map<Tin, D, AHR>, (KFnB)k_map_b<Tin, D, AHR>}; }
+static KPair map_pair() { return KPair{(KFn)k_map<Tin, D, AHR>, (KFnB)k_map_b<Tin, D, AHR>, mc_map_threads(AHR)}; }
 
 template <typename Tin, bool AHR>
 static KPair pick_map_t(int D, int path)
 {
-    if (path) return KPair{(KFn)k_map_generic<Tin, AHR>, (KFnB)k_map_generic_b<Tin, AHR>};
+    if (path) return KPair{(KFn)k_map_generic<Tin, AHR>, (KFnB)k_map_generic_b<Tin, AHR>, MC_T};
     switch (D) {
     case 1: return map_pair<Tin, 1, AHR>();
     case 2: return map_pair<Tin, 2, AHR>();

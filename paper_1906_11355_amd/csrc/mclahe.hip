@@ -134,13 +134,13 @@ static mclahe_status derive(mclahe_plan_s *p)
     const mclahe_tuning &t = p->tune;
 
     // ---- histogram units --------------------------------------------------
-    int R = t.hist_copies > 0 ? t.hist_copies : 2;   // 2 replicas: fastest on Poisson count data
+    int R = t.hist_copies > 0 ? t.hist_copies : 1;   // one replica: as fast as two, less LDS
     if (R != 1 && R != 2 && R != 4 && R != 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "hist_copies must be 1, 2, 4 or 8");
     const size_t hdr = hist_lds_header();
-    while (R > 1 && hdr + (size_t)p->nb * R * 4 > MC_LDS_BUDGET) R /= 2;
-    if (hdr + (size_t)p->nb * 4 > MC_LDS_BUDGET)
+    while (R > 1 && hdr + (size_t)mc_hist_slot_stride(p->nb, R) * 4 > MC_LDS_BUDGET) R /= 2;
+    if (hdr + (size_t)mc_hist_slot_stride(p->nb, 1) * 4 > MC_LDS_BUDGET)
         return fail(MCLAHE_ERROR_NOT_SUPPORTED, "n_bins=%d needs more LDS than a work-group may use", p->nb);
-    int Gmax = (int)std::min<size_t>(64, (MC_LDS_BUDGET - hdr) / ((size_t)p->nb * R * 4));
+    int Gmax = (int)std::min<size_t>(64, (MC_LDS_BUDGET - hdr) / ((size_t)mc_hist_slot_stride(p->nb, R) * 4));
     Gmax = std::max(1, std::min(Gmax, al.n));
     int G = 0;
     for (int g = Gmax; g >= 1; --g) {
@@ -184,6 +184,8 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.hR = R;
     // hist_peel: 0 = default (no aggregation), k >= 1 = k - 1 rounds
     v.hPeel = t.hist_peel > 0 ? std::min(t.hist_peel - 1, 2) : 0;
+    // hist_hotbin: 0 = default (off), 1 = off, 2 = on
+    v.hHot = t.hist_hotbin == 2 ? 1 : 0;
     v.hCols = 1;
     int64_t omax_h = 1, rmax_h = 1;
     for (int i = 0; i < D - 1; ++i) {
@@ -256,6 +258,18 @@ static mclahe_status derive(mclahe_plan_s *p)
     }
     v.mG = mG;
     v.mP = mP;
+    // streaming stores only when every unit writes whole rows of whole lines
+    v.ntst = 0;
+    if (fast && mP == 1) {   // streaming stores when every row segment is whole 64-byte blocks
+        bool ok = ((int64_t)al.s * (int64_t)esize(p->out_dt)) % 64 == 0;
+        for (int cA = 0; cA < ncl && ok; cA += mG) {
+            int xs, xe, tmp;
+            mc_cell_range(al, cA, xs, tmp);
+            mc_cell_range(al, std::min(cA + mG, ncl) - 1, tmp, xe);
+            ok = ((int64_t)xs * (int64_t)esize(p->out_dt)) % 64 == 0 && ((int64_t)xe * (int64_t)esize(p->out_dt)) % 64 == 0;
+        }
+        v.ntst = ok ? 1 : 0;
+    }
     v.mS = mP > 1 ? ncl * mP : (ncl + mG - 1) / mG;
     v.mCols = 1;
     int64_t omax_m = 1, rmax_m = 1;
@@ -295,7 +309,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     p->total = o;
 
     p->lds_range = 2 * MC_T * 4;
-    p->lds_hist = hdr + (size_t)v.hG * v.nb * v.hR * 4;
+    p->lds_hist = hdr + (size_t)v.hG * mc_hist_slot_stride(v.nb, v.hR) * 4;
     p->lds_clip = MC_T * 8;
     p->lds_map = fast ? otab + map_lut_bytes(p, v.mG) : 0;
     return MCLAHE_SUCCESS;
@@ -356,7 +370,7 @@ static KPair phase_kernels(const mclahe_plan_s *p, const McVol &v, int ph, size_
              : dt == MC_U16 ? mc_pick_hist_u16(ahr, false, v.hPeel) : mc_pick_hist_f32(ahr, false, v.hPeel);
     case 2:
         lds = p->lds_clip;
-        return KPair{(KFn)k_clip, (KFnB)k_clip_b};
+        return KPair{(KFn)k_clip, (KFnB)k_clip_b, MC_T};
     default:
         lds = p->lds_map;
         return dt == MC_U8 ? mc_pick_map_u8(p->D, ahr, v.path)
@@ -364,10 +378,10 @@ static KPair phase_kernels(const mclahe_plan_s *p, const McVol &v, int ph, size_
     }
 }
 
-static mclahe_status launch(KFn f, uint32_t grid, size_t lds, hipStream_t st, const McVol &v)
+static mclahe_status launch(KFn f, uint32_t grid, int threads, size_t lds, hipStream_t st, const McVol &v)
 {
     if (grid == 0) return MCLAHE_SUCCESS;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(MC_T), lds, st, v);
+    hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds, st, v);
     HIPCHK(hipGetLastError());
     return MCLAHE_SUCCESS;
 }
@@ -380,7 +394,7 @@ static mclahe_status run_plain(const mclahe_plan_s *p, const McVol &v, hipStream
         if (ev) HIPCHK(hipEventRecord(ev[ph], st));
         size_t lds = 0;
         const KPair k = phase_kernels(p, v, ph, lds);
-        if ((s = launch(k.plain, mc_phase_units(v, ph), lds, st, v))) return s;
+        if ((s = launch(k.plain, mc_phase_units(v, ph), k.threads, lds, st, v))) return s;
     }
     if (ev) HIPCHK(hipEventRecord(ev[MC_PHASES], st));
     return MCLAHE_SUCCESS;
@@ -398,6 +412,7 @@ struct mclahe_timer_s {
 struct BatchLaunch {
     int phase;
     KFnB fn;
+    int threads;
     size_t lds;
     std::vector<uint32_t> vols;   // volume indices
     std::vector<uint32_t> pre;    // unit prefix sums
@@ -429,7 +444,7 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout
             for (size_t j = first; j < L.launches.size(); ++j)
                 if (L.launches[j].fn == k.batch) bl = &L.launches[j];
             if (!bl) {
-                L.launches.push_back(BatchLaunch{ph, k.batch, 0, {}, {0}});
+                L.launches.push_back(BatchLaunch{ph, k.batch, k.threads, 0, {}, {0}});
                 bl = &L.launches.back();
             }
             bl->lds = std::max(bl->lds, lds);
@@ -530,7 +545,7 @@ static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std:
         hipKernelNodeParams kp = {};
         kp.func = (void *)bl.fn;
         kp.gridDim = dim3(recs[j].units);
-        kp.blockDim = dim3(MC_T);
+        kp.blockDim = dim3(bl.threads);
         kp.sharedMemBytes = (unsigned)bl.lds;
         kp.kernelParams = args;
         hipGraphNode_t node;
@@ -566,7 +581,7 @@ static void tune_cache_load()
     char key[512];
     mclahe_tuning t;
     while (fscanf(fp, "%511s %d %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
-                  &t.map_rows_split, &t.map_group, &t.reserved) == 7)
+                  &t.map_rows_split, &t.map_group, &t.hist_hotbin) == 7)
         g_tune_cache[key] = t;
     fclose(fp);
 }
@@ -579,7 +594,7 @@ static void tune_cache_store(const std::string &key, const mclahe_tuning &t)
     FILE *fp = fopen(f, "a");
     if (!fp) return;
     fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
-            t.map_rows_split, t.map_group, t.reserved);
+            t.map_rows_split, t.map_group, t.hist_hotbin);
     fclose(fp);
 }
 
@@ -755,7 +770,7 @@ mclahe_status mclahe_plan_get_tuning(mclahe_plan_t p, mclahe_tuning *t)
     t->hist_peel = p->v.hPeel + 1;
     t->map_rows_split = p->v.mCr;
     t->map_group = p->v.mG;
-    t->reserved = p->tune.reserved;
+    t->hist_hotbin = p->v.hHot ? 2 : 1;
     return MCLAHE_SUCCESS;
 }
 
@@ -763,7 +778,7 @@ mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
 {
     if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
     if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->hist_peel < 0 ||
-        t->hist_peel > 3 || t->reserved < 0 || t->hist_copies < 0)
+        t->hist_peel > 3 || t->hist_hotbin < 0 || t->hist_hotbin > 2 || t->hist_copies < 0)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "tuning fields must be >= 0 (hist_peel <= 3)");
     const mclahe_tuning old = p->tune;
     p->tune = *t;

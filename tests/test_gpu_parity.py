@@ -117,7 +117,8 @@ def test_in_place():
 @pytest.mark.parametrize("tuning", [
     dict(hist_copies=1, hist_peel=1), dict(hist_copies=4, hist_peel=3, hist_rows_split=1),
     dict(hist_copies=8, hist_peel=2, hist_rows_split=37), dict(map_group=1, map_rows_split=1),
-    dict(map_group=3, map_rows_split=11), dict(hist_copies=2, map_group=2, map_rows_split=64)])
+    dict(map_group=3, map_rows_split=11), dict(hist_copies=2, map_group=2, map_rows_split=64),
+    dict(hist_hotbin=1), dict(hist_hotbin=2, hist_peel=2, hist_copies=4)])
 def test_tuning_does_not_change_bits(tuning):
     rng = np.random.default_rng(7)
     x = rng.poisson(2.0, size=(40, 36, 30, 16)).astype(np.float32)
@@ -184,3 +185,15 @@ def test_cfg2_3d_f32_ahr_full():
     from paper_1906_11355_amd import synth
     x = synth.gen_3d((256, 256, 128), 2)
     _case(x, (32, 32, 16), 256, 0.02, "kernel")
+
+
+_CFG3 = {}
+
+
+@pytest.mark.parametrize("mode", ["global", "kernel"])
+def test_cfg3_4d_f32_full(mode):
+    """The headline workload at full size, every voxel against the oracle."""
+    from paper_1906_11355_amd import synth
+    if "x" not in _CFG3:
+        _CFG3["x"] = synth.gen_4d((256, 256, 128, 32), 3)
+    _case(_CFG3["x"], (32, 32, 16, 8), 512, 0.02, mode)
