@@ -134,7 +134,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     const mclahe_tuning &t = p->tune;
 
     // ---- histogram units --------------------------------------------------
-    int R = t.hist_copies > 0 ? t.hist_copies : 1;   // one replica: as fast as two, less LDS
+    int R = t.hist_copies > 0 ? t.hist_copies : 2;   // 2 replicas: fastest measured on Poisson counts
     if (R != 1 && R != 2 && R != 4 && R != 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "hist_copies must be 1, 2, 4 or 8");
     const size_t hdr = hist_lds_header();
     while (R > 1 && hdr + (size_t)mc_hist_slot_stride(p->nb, R) * 4 > MC_LDS_BUDGET) R /= 2;
