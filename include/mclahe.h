@@ -175,12 +175,13 @@ mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans
                                                uint64_t *offsets);
 
 /* Enhance n independent volumes (mixed ndim, shape, dtype, parameters) as
- * one batch: each of the four passes is ONE launch over the work units of
- * every volume, and the four launches are replayed from a hipGraph cached
- * per batch signature (plans and workspace address), after one stream-ordered
- * copy of the batch's descriptor table into the workspace.  Each output (and
- * each intermediate array) is bit-identical to mclahe_run of the same plan.
- * The plans must stay alive until the work has completed on the stream.    */
+ * one batch: each pass is ONE launch per kernel class (volumes that run the
+ * same kernel template) over the work units of all its volumes, after one
+ * stream-ordered copy of the batch's descriptor table into the workspace.
+ * A batch signature (plans and workspace address) seen again is replayed
+ * from a hipGraph (LRU cache of 16); a new one is launched directly.  Each
+ * output (and each intermediate array) is bit-identical to mclahe_run of the
+ * same plan.  The plans must stay alive until the work has completed.     */
 mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans,
                                  const void *const *d_in, void *const *d_out,
                                  void *d_workspace, size_t workspace_bytes,

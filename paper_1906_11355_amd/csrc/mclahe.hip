@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <new>
 #include <string>
 #include <vector>
@@ -499,9 +500,10 @@ static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins
     }
 }
 
-// A cached graph of the batched launches for one batch signature (plans and
-// workspace address), with a ring of pinned host images of the descriptor
-// table (a slot is reused only after the copy that read it has run).
+// A batch signature (plans and workspace address) seen for the first time is
+// launched directly; when it repeats, its launches are captured in a graph,
+// kept in a small LRU cache with a ring of pinned host images of the
+// descriptor table (a slot is reused only after the copy that read it ran).
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -510,10 +512,57 @@ struct GraphEntry {
     std::vector<bool> used;
     int next = 0;
     size_t bytes = 0;
+    uint64_t last_use = 0;
 };
 
 static std::mutex g_graph_mu;
 static std::map<std::string, GraphEntry *> g_graphs;
+static std::set<std::string> g_seen;      // batch signatures launched directly once
+static uint64_t g_tick = 0;
+static const size_t kGraphCacheMax = 16;
+
+static void destroy_graph(GraphEntry *g)
+{
+    for (size_t r = 0; r < g->ev.size(); ++r) {
+        if (g->used[r]) (void)hipEventSynchronize(g->ev[r]);
+        (void)hipEventDestroy(g->ev[r]);
+    }
+    for (char *h : g->host) (void)hipHostFree(h);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+// Pinned staging ring for descriptor tables of directly launched batches: a
+// slot is reused (or grown) only after the copy that read it has completed.
+struct StageSlot {
+    char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+static StageSlot g_stage[8];
+static int g_stage_next = 0;
+
+static mclahe_status stage_table(const std::vector<char> &img, void *dst, hipStream_t st)
+{
+    StageSlot &sl = g_stage[g_stage_next];
+    g_stage_next = (g_stage_next + 1) % 8;
+    if (!sl.ev) HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    if (sl.used) HIPCHK(hipEventSynchronize(sl.ev));
+    if (sl.cap < img.size()) {
+        if (sl.host) HIPCHK(hipHostFree(sl.host));
+        sl.host = nullptr;
+        sl.cap = 0;
+        HIPCHK(hipHostMalloc((void **)&sl.host, img.size(), hipHostMallocDefault));
+        sl.cap = img.size();
+    }
+    memcpy(sl.host, img.data(), img.size());
+    HIPCHK(hipMemcpyAsync(dst, sl.host, img.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(sl.ev, st));
+    sl.used = true;
+    return MCLAHE_SUCCESS;
+}
 
 // Graph: the launches of one pass are independent branches; every launch of
 // pass ph depends on every launch of the previous non-empty pass.
@@ -959,10 +1008,37 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
     std::string key = std::to_string((uintptr_t)ws) + ":" + std::to_string(n);
     for (int i = 0; i < n; ++i) key += ":" + std::to_string((uintptr_t)plans[i]) + "/" + plan_key(plans[i]);
     std::lock_guard<std::mutex> lk(g_graph_mu);
-    GraphEntry *g;
+    ++g_tick;
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
-        g = new GraphEntry();
+        if (!g_seen.count(key)) {
+            // first sight of this batch: direct launches, remember the signature
+            if (g_seen.size() > 4096) g_seen.clear();
+            g_seen.insert(key);
+            if ((s = stage_table(img, ws + L.o_table, st))) return s;
+            const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
+            const uint32_t *idx_dev = (const uint32_t *)(ws + L.o_table + L.o_idx);
+            const McVol *vols_dev = (const McVol *)(ws + L.o_table + L.o_vols);
+            for (size_t j = 0; j < L.launches.size(); ++j) {
+                const BatchLaunch &bl = L.launches[j];
+                if (bl.lds > 64 * 1024)
+                    HIPCHK(hipFuncSetAttribute((const void *)bl.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)bl.lds));
+                McBatchSrc src{vols_dev, idx_dev + recs[j].list, idx_dev + recs[j].pre, recs[j].n, 0};
+                hipLaunchKernelGGL(bl.fn, dim3(recs[j].units), dim3(bl.threads), bl.lds, st, src);
+                HIPCHK(hipGetLastError());
+            }
+            return MCLAHE_SUCCESS;
+        }
+        // repeated batch: capture it as a graph (bounded cache, LRU eviction)
+        if (g_graphs.size() >= kGraphCacheMax) {
+            auto victim = g_graphs.begin();
+            for (auto e = g_graphs.begin(); e != g_graphs.end(); ++e)
+                if (e->second->last_use < victim->second->last_use) victim = e;
+            destroy_graph(victim->second);
+            g_graphs.erase(victim);
+        }
+        GraphEntry *g = new GraphEntry();
         g->bytes = img.size();
         for (int r = 0; r < 4; ++r) {
             char *hb = nullptr;
@@ -974,11 +1050,14 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
             g->used.push_back(false);
         }
         s = build_graph(g, L, img, ws);
-        if (s) return s;
-        g_graphs[key] = g;
-    } else {
-        g = it->second;
+        if (s) {
+            destroy_graph(g);
+            return s;
+        }
+        it = g_graphs.emplace(key, g).first;
     }
+    GraphEntry *g = it->second;
+    g->last_use = g_tick;
     const int slot = g->next;
     g->next = (g->next + 1) % (int)g->host.size();
     if (g->used[slot]) HIPCHK(hipEventSynchronize(g->ev[slot]));
