@@ -7,10 +7,15 @@ histogram range; synthetic data from paper_1906_11355_amd.synth (seed 3).
 
 A step is one full pass of the hot path on that volume, inputs resident in
 HBM: range -> per-kernel histograms -> clip/CDF/LUT -> 2^D-corner
-interpolation (mclahe_run).  Prints one JSON line.
+interpolation (mclahe_run).  Prints one JSON line; beside the headline it
+holds the mixed batch of 64 volumes (batched launches vs one plain launch
+per volume) and the serving loop (Poisson arrivals swept over rates:
+continuous batching vs a FIFO of plain serial launches, p50/p99 latency).
+Progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--mode global|kernel]
-                    [--no-cpu-baseline] [--calib-copy] [--batched]
+                    [--no-cpu-baseline] [--calib-copy] [--skip-batched]
+                    [--skip-serve] [--rates 10,100,500,1000,2000]
 """
 from __future__ import annotations
 
@@ -65,9 +70,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--batched", action="store_true",
-                    help="also time the mixed batch: batched launches vs per-volume launches")
+    ap.add_argument("--skip-batched", action="store_true",
+                    help="leave out the mixed batch (batched launches vs per-volume launches)")
+    ap.add_argument("--skip-serve", action="store_true", help="leave out the serving sweep")
+    ap.add_argument("--rates", default="10,100,500,1000,2000", help="serving arrival rates, req/s")
+    ap.add_argument("--serve-budget-gib", type=float, default=24.0, help="serving HBM arena")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gen_mix_items(synth):
+    """The 64-volume mix (seeded); numpy releases the GIL, so threads help."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synth.mix_spec(64, 4)
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(synth.gen_item, specs))
 
 
 def main():
@@ -80,10 +100,12 @@ def main():
     import torch
     from paper_1906_11355_amd import _lib, synth
 
-    dev = torch.device("cuda:0")
     t_gen = time.perf_counter()
     x = synth.gen_4d(SHAPE, 3)
+    items = None if (args.skip_batched and args.skip_serve) else gen_mix_items(synth)
     t_gen = time.perf_counter() - t_gen
+    log(f"inputs generated in {t_gen:.1f} s")
+    dev = torch.device("cuda:0")
     xt = torch.from_numpy(x).to(dev)
     out = torch.empty_like(xt)
     plan = _lib.Plan(SHAPE, KSIZE, NBINS, CLIP, args.mode, in_dtype="float32", out_dtype="float32")
@@ -147,8 +169,16 @@ def main():
         "input_gen_s": round(t_gen, 1),
     }
 
-    if args.batched:
-        res["batched"] = bench_batched(torch, np, _lib, synth, dev)
+    log(f"headline: {ms:.4f} ms/step, {value:.1f} Gvoxel/s")
+    g_out = out.cpu().numpy()
+    del out, ws, xt
+    torch.cuda.empty_cache()
+    if not args.skip_batched:
+        res["batched"] = bench_batched(torch, np, _lib, items, dev)
+        log(f"batched: {res['batched']}")
+    if not args.skip_serve:
+        rates = [float(r) for r in args.rates.split(",") if r]
+        res["serve"] = bench_serve(torch, np, items, dev, rates, args.serve_budget_gib)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -159,17 +189,12 @@ def main():
         res["cpu_baseline"] = {"value": round(V / dt / 1e9, 5), "unit": "Gvoxel/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"the full {'x'.join(map(str, SHAPE))} volume, one step ({dt:.1f} s)"}
-        g = out.cpu().numpy()
-        res["parity_vs_oracle"] = {"max_abs_out": float(np.abs(g.astype(np.float64) - r["out"]).max())}
+        res["parity_vs_oracle"] = {"max_abs_out": float(np.abs(g_out.astype(np.float64) - r["out"]).max())}
     print(json.dumps(res), flush=True)
 
 
-def bench_batched(torch, np, _lib, synth, dev, n=None):
+def bench_batched(torch, np, _lib, items, dev):
     """Mixed batch: one launch per pass for all volumes vs per-volume launches."""
-    specs = synth.mix_spec(64, 4)
-    if n:
-        specs = specs[:n]
-    items = [synth.gen_item(s) for s in specs]
     xs = [torch.from_numpy(it.x).to(dev) for it in items]
     plans = [_lib.Plan(it.x.shape, it.kernel_size, it.n_bins, it.clip_limit,
                        "kernel" if it.adaptive else "global", in_dtype=str(it.x.dtype),
@@ -203,6 +228,68 @@ def bench_batched(torch, np, _lib, synth, dev, n=None):
     return {"volumes": len(xs), "voxels": vox, "plain_ms": round(ms_p, 3), "batched_ms": round(ms_b, 3),
             "plain_Gvox_s": round(vox / ms_p / 1e6, 2), "batched_Gvox_s": round(vox / ms_b / 1e6, 2),
             "bit_identical": bool(same)}
+
+
+def bench_serve(torch, np, items, dev, rates, budget_gib):
+    """Serving sweep over Poisson arrival rates.
+
+    served: continuous batching, 2 compute streams, up to 64 requests in
+    flight, steps of up to 32; serial: one request at a time, plain launch.
+    Latency runs from the scheduled arrival to the step's completion event
+    (input copy from pinned host memory included; the output stays in HBM).
+    A second, shorter sweep takes inputs already resident in HBM."""
+    from paper_1906_11355_amd.serve import DeviceBackend, Request, Server, make_requests
+    budget = int(budget_gib * (1 << 30))
+
+    def pool_of(resident):
+        return [dict(shape=it.x.shape, kernel_size=it.kernel_size, clip_limit=it.clip_limit,
+                     adaptive=it.adaptive, in_dtype=str(it.x.dtype),
+                     payload=(torch.from_numpy(it.x).to(dev) if resident
+                              else torch.from_numpy(it.x).pin_memory())) for it in items]
+
+    def run(be, pool, rate, n, serial, seed):
+        reqs = make_requests(pool, rate, n, seed)
+        srv = Server(be, budget, max_slots=1, max_batch=1) if serial else \
+            Server(be, budget, max_slots=64, max_batch=32)
+        t0 = be.clock() + 0.005
+        for r in reqs:
+            r.arrival += t0
+        rep = srv.run(reqs)
+        if rep.n_done != n:
+            raise RuntimeError(f"serving run lost requests: {rep}")
+        d = rep.as_dict()
+        return {k: d[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "gvox_s", "makespan_s", "steps",
+                                  "mean_batch", "max_batch", "max_concurrent_steps")}
+
+    out = {"latency": "scheduled arrival -> output-ready event; input copy included, output stays in HBM",
+           "budget_gib": budget_gib, "served": "2 streams, <=64 in flight, <=32 per step, batched launches",
+           "serial": "FIFO, one request at a time, plain launch", "pool": len(items), "sweep": []}
+    for resident in (False, True):
+        pool = pool_of(resident)
+        be_s = DeviceBackend(budget, n_streams=2, h2d=not resident)
+        be_p = DeviceBackend(budget, n_streams=1, h2d=not resident, plain=True)
+        for be in (be_s, be_p):        # plans (host objects) made before the clock runs
+            for it in pool:
+                be.plan(Request(0, 0.0, tuple(it["shape"]), tuple(it["kernel_size"]),
+                                clip_limit=it["clip_limit"], adaptive=it["adaptive"], in_dtype=it["in_dtype"]))
+        run(be_s, pool, float("inf"), 32, False, 99)       # warm-up (first graph/table staging)
+        run(be_p, pool, float("inf"), 8, True, 99)
+        rlist = (list(rates) if not resident else [r for r in rates if r >= 1000]) + [float("inf")]
+        for rate in rlist:
+            n = 256 if rate == float("inf") else int(min(1200, max(32, rate * 1.2)))
+            row = {"rate_hz": "burst" if rate == float("inf") else rate, "n": n,
+                   "inputs": "hbm" if resident else "host_pinned"}
+            row["served"] = run(be_s, pool, rate, n, False, 7)
+            row["serial"] = run(be_p, pool, rate, n, True, 7)
+            out["sweep"].append(row)
+            log(f"serve {row['inputs']} rate={row['rate_hz']} n={n}: served p50/p99 "
+                f"{row['served']['p50_ms']:.3f}/{row['served']['p99_ms']:.3f} ms "
+                f"{row['served']['gvox_s']:.2f} Gvox/s | serial {row['serial']['p50_ms']:.3f}/"
+                f"{row['serial']['p99_ms']:.3f} ms {row['serial']['gvox_s']:.2f} Gvox/s")
+        del be_s, be_p, pool
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -46,7 +46,8 @@
  *
  * Memory and ownership.  The caller owns every device buffer: input, output
  * and a workspace of mclahe_workspace_size() bytes (256-byte aligned).  The
- * library never allocates device memory in mclahe_run or mclahe_run_batched;
+ * library never allocates device memory in a run call (the batched calls
+ * allocate pinned host staging buffers and keep cached graphs);
  * mclahe_plan allocates host memory only.  Arrays are C-contiguous, last axis
  * fastest.  Input and output may alias only if their element sizes match.
  * All run calls are asynchronous on the given HIP stream (NULL = the default
@@ -178,14 +179,34 @@ mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans
  * one batch: each pass is ONE launch per kernel class (volumes that run the
  * same kernel template) over the work units of all its volumes, after one
  * stream-ordered copy of the batch's descriptor table into the workspace.
- * A batch signature (plans and workspace address) seen again is replayed
- * from a hipGraph (LRU cache of 16); a new one is launched directly.  Each
- * output (and each intermediate array) is bit-identical to mclahe_run of the
- * same plan.  The plans must stay alive until the work has completed.     */
+ * A batch whose structure (table address; kernel, volume count, grid, block
+ * and LDS size of every launch) was seen before is replayed from a hipGraph
+ * (LRU cache of 16); a new one is launched directly.  Each output (and each
+ * intermediate array) is bit-identical to mclahe_run of the same plan.
+ * Calls are stream-ordered; two calls in flight on different streams must
+ * not share a workspace.                                                    */
 mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans,
                                  const void *const *d_in, void *const *d_out,
                                  void *d_workspace, size_t workspace_bytes,
                                  void *hip_stream);
+
+/* Bytes of a batch's descriptor table (the head of a batched workspace,
+ * before the first volume's own workspace).                                 */
+mclahe_status mclahe_batched_table_size(int n, const mclahe_plan_t *plans, size_t *bytes);
+
+/* mclahe_run_batched with the workspace split: volume i keeps its
+ * histograms, clipped counts, LUTs and range in its own workspace d_ws[i]
+ * of ws_bytes[i] >= mclahe_workspace_size(plans[i]) bytes, and the table
+ * goes to d_table (table_bytes >= mclahe_batched_table_size, 256-byte
+ * aligned).  For a serving loop that gives each request its own device
+ * state.  The buffers must not overlap each other or any input/output
+ * (except an in-place volume's own input and output).  Same kernels and the
+ * same bits as mclahe_run_batched; errors as there, per volume.            */
+mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans,
+                                       const void *const *d_in, void *const *d_out,
+                                       void *const *d_ws, const size_t *ws_bytes,
+                                       void *d_table, size_t table_bytes,
+                                       void *hip_stream);
 
 /* Host image of the batch descriptor table that mclahe_run_batched would
  * upload for these arguments (no device call), for inspection and tests.

@@ -76,6 +76,9 @@ def _load():
         "mclahe_batched_workspace_offsets": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_uint64)],
         "mclahe_run_batched": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
                                ctypes.c_size_t, P],
+        "mclahe_batched_table_size": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_run_batched_split": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t), P, ctypes.c_size_t, P],
         "mclahe_batched_table": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
                                  P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_autotune_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
@@ -249,6 +252,24 @@ def run_batched_ptr(plans, d_ins, d_outs, d_ws: int, ws_bytes: int, stream: int 
     ins = (ctypes.c_void_p * n)(*d_ins)
     outs = (ctypes.c_void_p * n)(*d_outs)
     _check(lib.mclahe_run_batched(n, _plans_array(plans), ins, outs, d_ws, ws_bytes, stream))
+
+
+def batched_table_size(plans) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.mclahe_batched_table_size(len(plans), _plans_array(plans), ctypes.byref(n)))
+    return n.value
+
+
+def run_batched_split_ptr(plans, d_ins, d_outs, d_wss, ws_bytes, d_table: int, table_bytes: int,
+                          stream: int = 0):
+    """mclahe_run_batched_split: one workspace per volume plus a table buffer."""
+    n = len(plans)
+    ins = (ctypes.c_void_p * n)(*d_ins)
+    outs = (ctypes.c_void_p * n)(*d_outs)
+    wss = (ctypes.c_void_p * n)(*d_wss)
+    wsb = (ctypes.c_size_t * n)(*ws_bytes)
+    _check(lib.mclahe_run_batched_split(n, _plans_array(plans), ins, outs, wss, wsb, d_table, table_bytes,
+                                        stream))
 
 
 def batched_table(plans, d_ins, d_outs, d_ws: int) -> bytes:

@@ -475,15 +475,16 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout
 }
 
 // Host image of the table region [o_table, o_first).
+// Volume i's workspace is vol_ws[i].
 static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins, void *const *outs,
-                       char *ws, const BatchLayout &L, std::vector<char> &img)
+                       char *const *vol_ws, const BatchLayout &L, std::vector<char> &img)
 {
     img.assign(L.o_first - L.o_table, 0);
     McBatchHdr *h = (McBatchHdr *)img.data();
     McLaunchRec *recs = (McLaunchRec *)(img.data() + L.o_recs);
     uint32_t *idx = (uint32_t *)(img.data() + L.o_idx);
     McVol *vols = (McVol *)(img.data() + L.o_vols);
-    for (int i = 0; i < n; ++i) bind(plans[i], vols[i], ins[i], outs[i], ws + L.vol_off[i]);
+    for (int i = 0; i < n; ++i) bind(plans[i], vols[i], ins[i], outs[i], vol_ws[i]);
     h->nvol = (uint32_t)n;
     h->nlaunch = (uint32_t)L.launches.size();
     uint32_t k = 0;
@@ -500,8 +501,9 @@ static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins
     }
 }
 
-// A batch signature (plans and workspace address) seen for the first time is
-// launched directly; when it repeats, its launches are captured in a graph,
+// A batch signature (table address and the grid of every launch) seen for the
+// first time is launched directly; when it repeats, its launches are captured
+// in a graph,
 // kept in a small LRU cache with a ring of pinned host images of the
 // descriptor table (a slot is reused only after the copy that read it ran).
 struct GraphEntry {
@@ -566,12 +568,12 @@ static mclahe_status stage_table(const std::vector<char> &img, void *dst, hipStr
 
 // Graph: the launches of one pass are independent branches; every launch of
 // pass ph depends on every launch of the previous non-empty pass.
-static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std::vector<char> &img, char *ws)
+static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std::vector<char> &img, char *table)
 {
     HIPCHK(hipGraphCreate(&g->graph, 0));
     const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
-    const uint32_t *idx_dev = (const uint32_t *)(ws + L.o_table + L.o_idx);
-    const McVol *vols_dev = (const McVol *)(ws + L.o_table + L.o_vols);
+    const uint32_t *idx_dev = (const uint32_t *)(table + L.o_idx);
+    const McVol *vols_dev = (const McVol *)(table + L.o_vols);
     std::vector<hipGraphNode_t> prev, cur;
     int cur_phase = -1;
     for (size_t j = 0; j < L.launches.size(); ++j) {
@@ -972,6 +974,22 @@ mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans
     return MCLAHE_SUCCESS;
 }
 
+mclahe_status mclahe_batched_table_size(int n, const mclahe_plan_t *plans, size_t *bytes)
+{
+    if (!bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    *bytes = L.o_first - L.o_table;
+    return MCLAHE_SUCCESS;
+}
+
+static void vol_ws_in_place(int n, char *ws, const BatchLayout &L, std::vector<char *> &vws)
+{
+    vws.resize(n);
+    for (int i = 0; i < n; ++i) vws[i] = ws + L.vol_off[i];
+}
+
 mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans, const void *const *d_in,
                                    void *const *d_out, void *d_ws, void *host_image, size_t image_bytes,
                                    size_t *needed)
@@ -981,32 +999,33 @@ mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans, const void
     mclahe_status s = batch_layout(n, plans, L);
     if (s) return s;
     if (!d_in || !d_out || !needed) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    std::vector<char *> vws;
+    vol_ws_in_place(n, (char *)d_ws, L, vws);
     std::vector<char> img;
-    fill_table(n, plans, d_in, d_out, (char *)d_ws, L, img);
+    fill_table(n, plans, d_in, d_out, vws.data(), L, img);
     *needed = img.size();
     if (host_image) memcpy(host_image, img.data(), std::min(image_bytes, img.size()));
     return MCLAHE_SUCCESS;
 }
 
-mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *const *d_in,
-                                 void *const *d_out, void *d_ws, size_t wsb, void *stream)
+// Upload the table image to `table` and run the launches of L on st: directly
+// on the first sight of the batch's structure, from a cached graph after.
+// The key holds everything a graph bakes in: the table address and, per
+// launch, kernel, volume count, grid, block and LDS size.  Everything else a
+// kernel reads comes from the table uploaded before each replay.
+static mclahe_status batched_launch(const BatchLayout &L, const std::vector<char> &img, char *table,
+                                    hipStream_t st)
 {
-    g_err.clear();
-    BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
-    if (s) return s;
-    if (!d_in || !d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output arrays are NULL");
-    for (int i = 0; i < n; ++i) {
-        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws, wsb, L.total);
-        if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
+    mclahe_status s;
+    const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
+    std::string key = std::to_string((uintptr_t)table);
+    for (size_t j = 0; j < L.launches.size(); ++j) {
+        const BatchLaunch &bl = L.launches[j];
+        char buf[96];
+        snprintf(buf, sizeof buf, ":%zx/%u/%u/%d/%zu", (size_t)(uintptr_t)bl.fn, recs[j].n, recs[j].units,
+                 bl.threads, bl.lds);
+        key += buf;
     }
-    char *ws = (char *)d_ws;
-    hipStream_t st = (hipStream_t)stream;
-    std::vector<char> img;
-    fill_table(n, plans, d_in, d_out, ws, L, img);
-
-    std::string key = std::to_string((uintptr_t)ws) + ":" + std::to_string(n);
-    for (int i = 0; i < n; ++i) key += ":" + std::to_string((uintptr_t)plans[i]) + "/" + plan_key(plans[i]);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     ++g_tick;
     auto it = g_graphs.find(key);
@@ -1015,10 +1034,9 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
             // first sight of this batch: direct launches, remember the signature
             if (g_seen.size() > 4096) g_seen.clear();
             g_seen.insert(key);
-            if ((s = stage_table(img, ws + L.o_table, st))) return s;
-            const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
-            const uint32_t *idx_dev = (const uint32_t *)(ws + L.o_table + L.o_idx);
-            const McVol *vols_dev = (const McVol *)(ws + L.o_table + L.o_vols);
+            if ((s = stage_table(img, table, st))) return s;
+            const uint32_t *idx_dev = (const uint32_t *)(table + L.o_idx);
+            const McVol *vols_dev = (const McVol *)(table + L.o_vols);
             for (size_t j = 0; j < L.launches.size(); ++j) {
                 const BatchLaunch &bl = L.launches[j];
                 if (bl.lds > 64 * 1024)
@@ -1042,14 +1060,18 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
         g->bytes = img.size();
         for (int r = 0; r < 4; ++r) {
             char *hb = nullptr;
-            HIPCHK(hipHostMalloc((void **)&hb, g->bytes, hipHostMallocDefault));
+            hipEvent_t e = nullptr;
+            if (hipHostMalloc((void **)&hb, g->bytes, hipHostMallocDefault) != hipSuccess ||
+                hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                if (hb) (void)hipHostFree(hb);
+                destroy_graph(g);
+                return fail(MCLAHE_ERROR_HIP, "pinned staging buffer or event creation failed");
+            }
             g->host.push_back(hb);
-            hipEvent_t e;
-            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             g->ev.push_back(e);
             g->used.push_back(false);
         }
-        s = build_graph(g, L, img, ws);
+        s = build_graph(g, L, img, table);
         if (s) {
             destroy_graph(g);
             return s;
@@ -1062,11 +1084,55 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
     g->next = (g->next + 1) % (int)g->host.size();
     if (g->used[slot]) HIPCHK(hipEventSynchronize(g->ev[slot]));
     memcpy(g->host[slot], img.data(), g->bytes);
-    HIPCHK(hipMemcpyAsync(ws + L.o_table, g->host[slot], g->bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(table, g->host[slot], g->bytes, hipMemcpyHostToDevice, st));
     HIPCHK(hipEventRecord(g->ev[slot], st));
     g->used[slot] = true;
     HIPCHK(hipGraphLaunch(g->exec, st));
     return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                 void *const *d_out, void *d_ws, size_t wsb, void *stream)
+{
+    g_err.clear();
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    if (!d_in || !d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output arrays are NULL");
+    for (int i = 0; i < n; ++i) {
+        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws, wsb, L.total);
+        if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
+    }
+    char *ws = (char *)d_ws;
+    std::vector<char *> vws;
+    vol_ws_in_place(n, ws, L, vws);
+    std::vector<char> img;
+    fill_table(n, plans, d_in, d_out, vws.data(), L, img);
+    return batched_launch(L, img, ws + L.o_table, (hipStream_t)stream);
+}
+
+mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                       void *const *d_out, void *const *d_ws, const size_t *ws_bytes,
+                                       void *d_table, size_t table_bytes, void *stream)
+{
+    g_err.clear();
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, L);
+    if (s) return s;
+    if (!d_in || !d_out || !d_ws || !ws_bytes)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output/workspace arrays are NULL");
+    for (int i = 0; i < n; ++i) {
+        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws[i], ws_bytes[i], plans[i]->total);
+        if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
+    }
+    const size_t tb = L.o_first - L.o_table;
+    if (!d_table || ((uintptr_t)d_table % 256))
+        return fail(MCLAHE_ERROR_WORKSPACE, "descriptor table buffer NULL or not 256-byte aligned");
+    if (table_bytes < tb)
+        return fail(MCLAHE_ERROR_WORKSPACE, "descriptor table buffer too small: %zu < %zu bytes", table_bytes, tb);
+    std::vector<char> img;
+    fill_table(n, plans, d_in, d_out, (char *const *)d_ws, L, img);
+    return batched_launch(L, img, (char *)d_table, (hipStream_t)stream);
 }
 
 mclahe_status mclahe_autotune_workspace_size(mclahe_plan_t p, size_t *bytes)

@@ -151,6 +151,29 @@ def test_batched_workspace_offsets():
         assert o2 - o >= p.workspace_size()
 
 
+def test_batched_split_table_and_argument_checks():
+    plans = [Plan((64, 64), (16, 16), 64, 0.02), Plan((32, 32, 16), (8, 8, 4), 128, 0.01, "kernel")]
+    tb = _lib.batched_table_size(plans)
+    assert tb == _lib.batched_workspace_offsets(plans)[0] and tb % 256 == 0
+    ws = [p.workspace_size() for p in plans]
+    ins, outs, wss = [1 << 20, 2 << 20], [3 << 20, 4 << 20], [5 << 20, 6 << 20]
+    cases = [
+        (dict(d_table=0), _lib.WORKSPACE),                        # no table buffer
+        (dict(d_table=(7 << 20) + 64), _lib.WORKSPACE),           # misaligned table
+        (dict(table_bytes=tb - 1), _lib.WORKSPACE),               # table too small
+        (dict(ws_bytes=[ws[0], ws[1] - 1]), _lib.WORKSPACE),      # volume 1 workspace too small
+        (dict(d_wss=[5 << 20, (6 << 20) + 8]), _lib.WORKSPACE),   # volume 1 workspace misaligned
+        (dict(d_ins=[1 << 20, 0]), _lib.INVALID_VALUE),           # NULL input
+    ]
+    for kw, status in cases:
+        a = dict(d_ins=ins, d_outs=outs, d_wss=wss, ws_bytes=ws, d_table=7 << 20, table_bytes=tb)
+        a.update(kw)
+        with pytest.raises(MclaheError) as e:
+            _lib.run_batched_split_ptr(plans, a["d_ins"], a["d_outs"], a["d_wss"], a["ws_bytes"],
+                                       a["d_table"], a["table_bytes"])
+        assert e.value.status == status, (kw, e.value)
+
+
 def test_plan_count_limits():
     with pytest.raises(MclaheError):
         Plan((2 ** 20, 2 ** 20), (2 ** 19, 2 ** 19), 16, 0.1)   # kernel voxels >= 2^32
