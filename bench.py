@@ -167,6 +167,7 @@ def main():
                           "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
                           "frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "input_gen_s": round(t_gen, 1),
+        "kernel_source_hash": kernel_source_hash(),
     }
 
     log(f"headline: {ms:.4f} ms/step, {value:.1f} Gvoxel/s")
@@ -214,8 +215,18 @@ def bench_batched(torch, np, _lib, items, dev):
         _lib.run_batched_ptr(plans, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs_b],
                              wsb.data_ptr(), wsb.numel(), st)
 
+    ws_v = [torch.empty(p.workspace_size(), dtype=torch.uint8, device=dev) for p in plans]
+    outs_s = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in xs]
+    tbl = torch.empty(_lib.batched_table_size(plans), dtype=torch.uint8, device=dev)
+
+    def split():
+        _lib.run_batched_split_ptr(plans, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs_s],
+                                   [w.data_ptr() for w in ws_v], [w.numel() for w in ws_v], tbl.data_ptr(),
+                                   tbl.numel(), st)
+
     def timeit(f, k=10):
-        f()
+        f()          # first sight: direct launches
+        f()          # second: graph capture (batched entry)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(k):
@@ -223,9 +234,10 @@ def bench_batched(torch, np, _lib, items, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / k * 1e3
 
-    ms_p, ms_b = timeit(plain), timeit(batched)
-    same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_p))
+    ms_p, ms_b, ms_s = timeit(plain), timeit(batched), timeit(split)
+    same = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c in zip(outs_b, outs_p, outs_s))
     return {"volumes": len(xs), "voxels": vox, "plain_ms": round(ms_p, 3), "batched_ms": round(ms_b, 3),
+            "split_direct_ms": round(ms_s, 3),
             "plain_Gvox_s": round(vox / ms_p / 1e6, 2), "batched_Gvox_s": round(vox / ms_b / 1e6, 2),
             "bit_identical": bool(same)}
 
@@ -258,8 +270,19 @@ def bench_serve(torch, np, items, dev, rates, budget_gib):
         if rep.n_done != n:
             raise RuntimeError(f"serving run lost requests: {rep}")
         d = rep.as_dict()
-        return {k: d[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "gvox_s", "makespan_s", "steps",
-                                  "mean_batch", "max_batch", "max_concurrent_steps")}
+        row = {k: d[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "seen_p50_ms", "seen_p99_ms",
+                                 "gvox_s", "makespan_s", "steps", "mean_batch", "max_batch",
+                                 "max_concurrent_steps")}
+        # where the slowest request spent its time (ms)
+        w = max(reqs, key=lambda r: r.latency)
+        row["slowest"] = {"at_s": round(w.arrival - t0, 4), "rid": w.rid,
+                          "queue": round((w.t_admit - w.arrival) * 1e3, 3),
+                          "to_launch": round((w.t_launch - w.t_admit) * 1e3, 3),
+                          "run": round((w.t_ready - w.t_launch) * 1e3, 3),
+                          "seen": round((w.t_seen - w.arrival) * 1e3, 3),
+                          "step_size": sum(1 for r in reqs if r.step == w.step), "voxels": w.voxels}
+        row["ref_window_us"] = round(be.ref_window_s * 1e6, 1)
+        return row
 
     out = {"latency": "scheduled arrival -> output-ready event; input copy included, output stays in HBM",
            "budget_gib": budget_gib, "served": "2 streams, <=64 in flight, <=32 per step, batched launches",
@@ -282,6 +305,7 @@ def bench_serve(torch, np, items, dev, rates, budget_gib):
             row["served"] = run(be_s, pool, rate, n, False, 7)
             row["serial"] = run(be_p, pool, rate, n, True, 7)
             out["sweep"].append(row)
+            log(f"  slowest served: {row['served']['slowest']}  serial: {row['serial']['slowest']}")
             log(f"serve {row['inputs']} rate={row['rate_hz']} n={n}: served p50/p99 "
                 f"{row['served']['p50_ms']:.3f}/{row['served']['p99_ms']:.3f} ms "
                 f"{row['served']['gvox_s']:.2f} Gvox/s | serial {row['serial']['p50_ms']:.3f}/"

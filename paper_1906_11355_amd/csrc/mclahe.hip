@@ -1013,6 +1013,26 @@ mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans, const void
 // The key holds everything a graph bakes in: the table address and, per
 // launch, kernel, volume count, grid, block and LDS size.  Everything else a
 // kernel reads comes from the table uploaded before each replay.
+static mclahe_status batched_direct(const BatchLayout &L, const std::vector<char> &img, char *table,
+                                    hipStream_t st)
+{
+    mclahe_status s;
+    if ((s = stage_table(img, table, st))) return s;
+    const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
+    const uint32_t *idx_dev = (const uint32_t *)(table + L.o_idx);
+    const McVol *vols_dev = (const McVol *)(table + L.o_vols);
+    for (size_t j = 0; j < L.launches.size(); ++j) {
+        const BatchLaunch &bl = L.launches[j];
+        if (bl.lds > 64 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void *)bl.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bl.lds));
+        McBatchSrc src{vols_dev, idx_dev + recs[j].list, idx_dev + recs[j].pre, recs[j].n, 0};
+        hipLaunchKernelGGL(bl.fn, dim3(recs[j].units), dim3(bl.threads), bl.lds, st, src);
+        HIPCHK(hipGetLastError());
+    }
+    return MCLAHE_SUCCESS;
+}
+
 static mclahe_status batched_launch(const BatchLayout &L, const std::vector<char> &img, char *table,
                                     hipStream_t st)
 {
@@ -1034,19 +1054,7 @@ static mclahe_status batched_launch(const BatchLayout &L, const std::vector<char
             // first sight of this batch: direct launches, remember the signature
             if (g_seen.size() > 4096) g_seen.clear();
             g_seen.insert(key);
-            if ((s = stage_table(img, table, st))) return s;
-            const uint32_t *idx_dev = (const uint32_t *)(table + L.o_idx);
-            const McVol *vols_dev = (const McVol *)(table + L.o_vols);
-            for (size_t j = 0; j < L.launches.size(); ++j) {
-                const BatchLaunch &bl = L.launches[j];
-                if (bl.lds > 64 * 1024)
-                    HIPCHK(hipFuncSetAttribute((const void *)bl.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)bl.lds));
-                McBatchSrc src{vols_dev, idx_dev + recs[j].list, idx_dev + recs[j].pre, recs[j].n, 0};
-                hipLaunchKernelGGL(bl.fn, dim3(recs[j].units), dim3(bl.threads), bl.lds, st, src);
-                HIPCHK(hipGetLastError());
-            }
-            return MCLAHE_SUCCESS;
+            return batched_direct(L, img, table, st);
         }
         // repeated batch: capture it as a graph (bounded cache, LRU eviction)
         if (g_graphs.size() >= kGraphCacheMax) {
@@ -1132,7 +1140,8 @@ mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans, const 
         return fail(MCLAHE_ERROR_WORKSPACE, "descriptor table buffer too small: %zu < %zu bytes", table_bytes, tb);
     std::vector<char> img;
     fill_table(n, plans, d_in, d_out, (char *const *)d_ws, L, img);
-    return batched_launch(L, img, (char *)d_table, (hipStream_t)stream);
+    std::lock_guard<std::mutex> lk(g_graph_mu);      // the staging ring is shared
+    return batched_direct(L, img, (char *)d_table, (hipStream_t)stream);
 }
 
 mclahe_status mclahe_autotune_workspace_size(mclahe_plan_t p, size_t *bytes)
