@@ -15,7 +15,7 @@ Progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--mode global|kernel]
                     [--no-cpu-baseline] [--calib-copy] [--skip-batched]
-                    [--skip-serve] [--rates 10,100,500,1000,2000]
+                    [--skip-serve] [--skip-configs] [--rates 10,30,100,300,1000,2000]
 """
 from __future__ import annotations
 
@@ -73,7 +73,9 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true",
                     help="leave out the mixed batch (batched launches vs per-volume launches)")
     ap.add_argument("--skip-serve", action="store_true", help="leave out the serving sweep")
-    ap.add_argument("--rates", default="10,100,500,1000,2000", help="serving arrival rates, req/s")
+    ap.add_argument("--rates", default="10,30,100,300,1000,2000", help="serving arrival rates, req/s")
+    ap.add_argument("--skip-configs", action="store_true",
+                    help="leave out the 2D/3D configurations and the 4D per-kernel-range run")
     ap.add_argument("--serve-budget-gib", type=float, default=24.0, help="serving HBM arena")
     return ap.parse_args()
 
@@ -171,9 +173,14 @@ def main():
     }
 
     log(f"headline: {ms:.4f} ms/step, {value:.1f} Gvoxel/s")
+    res["lds_atomics"] = bench_lds_atomics(torch, dev, passes["hist"])
+    log(f"lds atomics: {res['lds_atomics']}")
     g_out = out.cpu().numpy()
     del out, ws, xt
     torch.cuda.empty_cache()
+    if not args.skip_configs:
+        res["configs"] = bench_configs(torch, np, _lib, synth, x, dev)
+        log(f"configs: {res['configs']}")
     if not args.skip_batched:
         res["batched"] = bench_batched(torch, np, _lib, items, dev)
         log(f"batched: {res['batched']}")
@@ -192,6 +199,101 @@ def main():
                                "sample": f"the full {'x'.join(map(str, SHAPE))} volume, one step ({dt:.1f} s)"}
         res["parity_vs_oracle"] = {"max_abs_out": float(np.abs(g_out.astype(np.float64) - r["out"]).max())}
     print(json.dumps(res), flush=True)
+
+
+def hist_lane_atomics(shape, ks) -> int:
+    """LDS atomic adds the histogram pass issues: one per original voxel and
+    kernel whose mirrored box holds it (padded duplicates are folded into an
+    integer weight, not extra atomics)."""
+    total = 1
+    for s, b in zip(shape, ks):
+        p = 2 * b - 1 - ((s - 1) % b)
+        p0 = p // 2
+        n = (s + p) // b
+        cnt = 0
+        for k in range(n):
+            xs = set()
+            for q in range(k * b, (k + 1) * b):
+                x = q - p0
+                x = -x - 1 if x < 0 else (2 * s - 1 - x if x >= s else x)
+                xs.add(x)
+            cnt += len(xs)
+        total *= cnt
+    return total
+
+
+def bench_lds_atomics(torch, dev, hist_ms):
+    """LDS atomic-add rate: probe peaks (conflict-free, 8 lanes per word, a
+    whole wave on one word) beside the histogram pass's achieved rate."""
+    import ctypes
+    path = os.path.join(HERE, "paper_1906_11355_amd", "libmclahe_probe.so")
+    lib = ctypes.CDLL(path)
+    f = lib.mclahe_probe_lds_atomics
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_ulonglong)]
+    f.restype = ctypes.c_int
+    st = torch.cuda.current_stream(dev).cuda_stream
+    out = {}
+    for ways, name in ((64, "conflict_free"), (8, "8_lanes_per_word"), (1, "64_lanes_per_word")):
+        best = None
+        for _ in range(3):
+            acc = torch.zeros(1, dtype=torch.int32, device=dev)
+            ms, ops = ctypes.c_float(), ctypes.c_ulonglong()
+            rc = f(ways, 4096, 4096, acc.data_ptr(), st, ctypes.byref(ms), ctypes.byref(ops))
+            if rc != 0:
+                raise RuntimeError(f"LDS probe failed ({rc})")
+            if int(acc.item()) & 0xFFFFFFFF != ops.value & 0xFFFFFFFF:
+                raise RuntimeError("LDS probe lost atomics")
+            rate = ops.value / (ms.value * 1e-3) / 1e9
+            best = rate if best is None else max(best, rate)
+        out[f"probe_{name}_Gops"] = round(best, 1)
+    n = hist_lane_atomics(SHAPE, KSIZE)
+    out["hist_lane_atomics_per_launch"] = n
+    out["hist_achieved_Gops"] = round(n / (hist_ms * 1e-3) / 1e9, 1)
+    out["hist_frac_of_conflict_free"] = round(out["hist_achieved_Gops"] / out["probe_conflict_free_Gops"], 4)
+    return out
+
+
+def time_plan(torch, _lib, plan, x, dev, steps):
+    """Mean ms per mclahe_run and per pass (HIP events), inputs in HBM."""
+    xt = torch.from_numpy(x).to(dev)
+    out = torch.empty(x.shape, dtype=torch.float32, device=dev)
+    ws = torch.empty(plan.workspace_size(), dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    ptrs = (xt.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), st)
+    for _ in range(3):
+        plan.run_ptr(*ptrs)
+    timer = _lib.Timer(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        timer.run(plan, *ptrs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    p = timer.read()
+    return ms, {k: round(p[k], 4) for k in ("range", "hist", "clip", "map")}
+
+
+def bench_configs(torch, np, _lib, synth, x4, dev):
+    """The 4D volume with per-kernel ranges, and the 2D and 3D configurations."""
+    out = {}
+    cases = [
+        ("4d_f32_256x256x128x32_kernel32x32x16x8_bins512_clip0.02_kernel_range", x4, KSIZE, NBINS, CLIP,
+         "kernel", 10),
+        ("2d_u8_512x512_kernel64x64_bins256_clip0.01_global", synth.gen_2d((512, 512), 1), (64, 64), 256, 0.01,
+         "global", 200),
+        ("3d_f32_256x256x128_kernel32x32x16_bins256_clip0.02_kernel_range", synth.gen_3d((256, 256, 128), 2),
+         (32, 32, 16), 256, 0.02, "kernel", 50),
+    ]
+    for name, x, ks, nb, clip, mode, steps in cases:
+        plan = _lib.Plan(x.shape, ks, nb, clip, mode, in_dtype=str(x.dtype), out_dtype="float32")
+        ms, passes = time_plan(torch, _lib, plan, x, dev, steps)
+        V = x.size
+        S = x.dtype.itemsize
+        out[name] = {"ms_per_step": round(ms, 4), "us_per_step": round(ms * 1e3, 1),
+                     "Gvoxel_s": round(V / ms / 1e6, 2), "pass_ms": passes,
+                     "path_frac_of_hbm": round(V * (3 * S + 4) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def bench_batched(torch, np, _lib, items, dev):
@@ -249,6 +351,7 @@ def bench_serve(torch, np, items, dev, rates, budget_gib):
     flight, steps of up to 32; serial: one request at a time, plain launch.
     Latency runs from the scheduled arrival to the step's completion event
     (input copy from pinned host memory included; the output stays in HBM).
+    1000 requests per rate, or about 3 s of arrivals at low rates.
     A second, shorter sweep takes inputs already resident in HBM."""
     from paper_1906_11355_amd.serve import DeviceBackend, Request, Server, make_requests
     budget = int(budget_gib * (1 << 30))
@@ -299,7 +402,8 @@ def bench_serve(torch, np, items, dev, rates, budget_gib):
         run(be_p, pool, float("inf"), 8, True, 99)
         rlist = (list(rates) if not resident else [r for r in rates if r >= 1000]) + [float("inf")]
         for rate in rlist:
-            n = 256 if rate == float("inf") else int(min(1200, max(32, rate * 1.2)))
+            # 1000 requests, or about 3 s of arrivals at low rates (at least 32)
+            n = 256 if rate == float("inf") else int(min(1000, max(32, rate * 3)))
             row = {"rate_hz": "burst" if rate == float("inf") else rate, "n": n,
                    "inputs": "hbm" if resident else "host_pinned"}
             row["served"] = run(be_s, pool, rate, n, False, 7)

@@ -16,6 +16,9 @@ LIB = os.path.join(HERE, "libmclahe.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["mclahe.hip", "k_plain_f32.hip", "k_plain_u16.hip", "k_plain_u8.hip"]
+# measurement tooling, a library of its own (not part of the MCLAHE ABI)
+PROBE_SOURCE = os.path.join(CSRC, "probe", "lds_atomics.hip")
+PROBE_LIB = os.path.join(HERE, "libmclahe_probe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -40,12 +43,28 @@ def _compile(src: str, csrc: str = CSRC, build_dir: str = BUILD) -> str:
     return obj
 
 
-def build(jobs: int | None = None, csrc: str = CSRC, build_dir: str = BUILD, lib: str = LIB) -> str:
+def build_probe(lib: str = PROBE_LIB) -> str:
+    """The LDS-atomic throughput probe used by the benchmark."""
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", PROBE_SOURCE, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("compile failed: probe")
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(jobs: int | None = None, csrc: str = CSRC, build_dir: str = BUILD, lib: str = LIB,
+          probe: bool = True) -> str:
     """Compile the sources in csrc into lib (defaults: this package, in-tree)."""
     os.makedirs(build_dir, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
+    jobs = jobs or min(len(SOURCES) + 1, max(1, os.cpu_count() or 1))
     with ThreadPoolExecutor(jobs) as ex:
+        fp = ex.submit(build_probe) if probe else None
         objs = list(ex.map(lambda s: _compile(s, csrc, build_dir), SOURCES))
+        if fp:
+            fp.result()
     tmp = lib + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, lib)
