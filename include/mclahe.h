@@ -113,13 +113,10 @@ typedef struct {
  *   hist_peel         : wavefront aggregation of colliding bins: 1 = off,
  *                       2 = one round, 3 = two rounds (0 = default)
  *   map_rows_split    : row chunks per cell column in the interpolation pass
- *   map_group         : interpolation cells per work unit along the last axis
- *   hist_hotbin       : register cache of each wave's most frequent bin in the
- *                       histogram pass: 1 = off, 2 = on (0 = default, off)  */
+ *   map_group         : interpolation cells per work unit along the last axis */
 typedef struct {
     int32_t hist_rows_split, hist_copies, hist_peel;
     int32_t map_rows_split, map_group;
-    int32_t hist_hotbin;
 } mclahe_tuning;
 
 /* Create a plan (host only; no device call).  Arguments follow the paper's
@@ -201,7 +198,9 @@ mclahe_status mclahe_batched_table_size(int n, const mclahe_plan_t *plans, size_
  * aligned).  For a serving loop that gives each request its own device
  * state.  The buffers must not overlap each other or any input/output
  * (except an in-place volume's own input and output).  Same kernels and the
- * same bits as mclahe_run_batched; errors as there, per volume.            */
+ * same bits as mclahe_run_batched; errors as there, per volume.  Launches
+ * directly every time (no graph capture: a serving loop's batches differ
+ * from step to step).                                                       */
 mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans,
                                        const void *const *d_in, void *const *d_out,
                                        void *const *d_ws, const size_t *ws_bytes,

@@ -124,7 +124,6 @@ struct McVol {
     int32_t hG, hP, hS, hCr;  // kernels per segment, parts per kernel,
                               // segments on the last axis, row chunks
     int32_t hR, hPeel;        // LDS replicas, aggregation rounds
-    int32_t hHot;             // register cache of each wave's most frequent bin
     int32_t ntst;             // 1: output row segments are whole 64-byte blocks
                               //    -> streaming (non-temporal) stores
     int64_t hCols;            // kernel columns (prod of n_i, i < D-1)

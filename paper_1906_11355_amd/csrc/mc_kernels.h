@@ -445,11 +445,13 @@ __device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int
 #pragma unroll
         for (int r = 0; r < PEEL; ++r) {
             if (!act) break;
+            // the leader index is wave-uniform: read its key and weight with
+            // v_readlane (no LDS traffic, unlike a shuffle)
             const int leader = __ffsll((long long)act) - 1;
-            const int lkey = __shfl(key, leader);
+            const int lkey = __builtin_amdgcn_readlane(key, leader);
             const bool same = (key == lkey);
             const unsigned long long sm = __ballot(same);
-            const uint32_t lval = __shfl(val, leader);
+            const uint32_t lval = (uint32_t)__builtin_amdgcn_readlane((int)val, leader);
             uint32_t sum;
             if (__ballot(same && val != lval) == 0ull) {
                 sum = (uint32_t)__popcll(sm) * lval;
@@ -567,15 +569,6 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     }
     const int cp = R > 1 ? (lane_id() & (R - 1)) : 0;
     const Tin *in = (const Tin *)d.in;
-    // Register cache of the wave's most frequent bin: hits on it are summed
-    // in registers and added to LDS once at the end, so the lanes that would
-    // all hit one LDS address (a dominant background value) issue no atomics.
-    // Integer sums: the histogram is unchanged, bit for bit.
-    int hot = -1;
-    uint32_t hc[V];
-#pragma unroll
-    for (int e = 0; e < V; ++e) hc[e] = 0;
-
     if (tact) {
         const int64_t rstart = r0 + trow;
         int64_t o = rstart / rs.in_len;
@@ -583,20 +576,19 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int64_t so = rpi / rs.in_len;
         const int sr = (int)(rpi - so * rs.in_len);
         const int64_t xoff = (int64_t)(c_lo + tch) * V;
-        // U rows per step: all their loads are issued before any is used, so
-        // each wave keeps U wide loads in flight
+        // U rows per step.  Software pipelined: the loads of the next U rows
+        // are issued before the current U rows are binned, so every wave
+        // keeps up to 2U wide loads in flight while it works.
         constexpr int U = V >= 8 ? 2 : 4;
-        for (int64_t row = rstart; row < r1; row += (int64_t)U * rpi) {
+        auto prep_load = [&](int64_t rw, uint32_t (&wr)[U], bool (&okk)[U], float (&fl)[U][V]) {
             int64_t offs[U];
-            uint32_t wrs[U];
-            bool ok[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                ok[u] = row + (int64_t)u * rpi < r1;
-                const HistOTab te = L.otab[ok[u] ? (int)(o - o0) : 0];
+                okk[u] = rw + (int64_t)u * rpi < r1;
+                const HistOTab te = L.otab[okk[u] ? (int)(o - o0) : 0];
                 const int xin = rs.in_lo + r;
                 offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
-                wrs[u] = te.w * (uint32_t)mc_mult(ib, xin);
+                wr[u] = te.w * (uint32_t)mc_mult(ib, xin);
                 r += sr;
                 o += so;
                 if (r >= rs.in_len) {
@@ -604,33 +596,27 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                     o += 1;
                 }
             }
-            float fu[U][V];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
+                if (okk[u]) load_chunk<Tin, V>(in + offs[u], fl[u]);
+        };
+        auto process = [&](int64_t rw, const uint32_t (&wr)[U], const bool (&okk)[U], const float (&fl)[U][V]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-            if (!ok[u]) break;
-            const float (&f)[V] = fu[u];
-            const uint32_t wrow = wrs[u];
+            if (!okk[u]) break;
+            const float (&f)[V] = fl[u];
+            const uint32_t wrow = wr[u];
+            // LDS word of (slot, bin) per element (replica 0; -1: no update)
+            // and its weight
+            int key[V];
+            uint32_t wk[V];
             if constexpr (!RANGE_ONLY) {
-                if (d.hHot && row == rstart && u == 0) {
-                    // the wave's most frequent bin among its lanes' first
-                    // values (ballots count active lanes only)
-                    const int b0 = m.s1[0] >= 0 ? bin_of(f[0], lo1[0], sc1[0], nbf, nbm1) : -1;
-                    unsigned long long act = __ballot(b0 >= 0);
-                    int best = 0;
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        if (!act) break;
-                        const int cand = __shfl(b0, __ffsll((long long)act) - 1);
-                        const unsigned long long sm = __ballot(b0 == cand);
-                        const int cnt = __popcll(sm);
-                        if (cnt > best) {
-                            best = cnt;
-                            hot = cand;
-                        }
-                        act &= ~sm;
+                for (int e = 0; e < V; ++e) {
+                    key[e] = -1;
+                    wk[e] = wrow * m.w1[e];
+                    if (m.s1[e] >= 0) {
+                        key[e] = m.s1[e] * SS + bin_of(f[e], lo1[e], sc1[e], nbf, nbm1) * R;
                     }
                 }
             }
@@ -649,13 +635,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                         }
                     }
                 } else {
-                    int key = -1;      // LDS word of (slot, bin), replica 0
-                    if (m.s1[e] >= 0) {
-                        const int b = bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
-                        if (b == hot) hc[e] += wrow * m.w1[e];
-                        else key = m.s1[e] * SS + b * R;
-                    }
-                    hist_add<PEEL>(L.h, key, wrow * m.w1[e], cp);
+                    hist_add<PEEL>(L.h, key[e], wk[e], cp);
                     if (m.extra[e]) {
                         uint32_t ex = m.extra[e];
                         while (ex) {
@@ -670,6 +650,24 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                 }
             }
             }
+        };
+        uint32_t wA[U], wB[U];
+        bool okA[U], okB[U];
+        float fA[U][V], fB[U][V];
+        const int64_t step = (int64_t)U * rpi;
+        int64_t row = rstart;
+        prep_load(row, wA, okA, fA);
+        for (;;) {
+            const int64_t nb = row + step;
+            if (nb < r1) prep_load(nb, wB, okB, fB);
+            process(row, wA, okA, fA);
+            row = nb;
+            if (row >= r1) break;
+            const int64_t na = row + step;
+            if (na < r1) prep_load(na, wA, okA, fA);
+            process(row, wB, okB, fB);
+            row = na;
+            if (row >= r1) break;
         }
     }
     if constexpr (RANGE_ONLY) {
@@ -680,10 +678,6 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                 atomicMax(&L.slot_mm[2 * m.s1[e] + 1], f2o(mx[e]));
             }
         }
-    } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-            if (hc[e]) atomicAdd(&L.h[m.s1[e] * SS + hot * R + cp], hc[e]);
     }
     __syncthreads();
     if constexpr (RANGE_ONLY) {
@@ -991,112 +985,249 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
     const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
-    // rows whose loads are in flight together (with NT threads and two
-    // units per CU this keeps ~64 KiB of loads in flight per CU)
-    constexpr int U = V >= 8 ? 2 : 4;
-    for (int64_t row = rstart; row < r1; row += (int64_t)U * rpi) {
-        int64_t offs[U];
-        float win[U];
-        float cfu[U][NOH];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            ok[u] = row + (int64_t)u * rpi < r1;
-            const OT &te = otab[ok[u] ? (int)(o - o0) : 0];
-            const int xin = rs.in_lo + r;
-            offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
-            win[u] = D >= 2 ? cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xin) : 0.f;
-#pragma unroll
-            for (int q = 0; q < NOH; ++q) cfu[u][q] = D >= 3 ? te.coef[q] : 1.0f;
-            r += sr;
-            o += so;
-            if (r >= rs.in_len) {
-                r -= rs.in_len;
-                o += 1;
+    // global range: software pipelined (below); per-kernel range keeps 2^D
+    // ranges in registers, so it runs one batch of rows at a time (else)
+    if constexpr (!AHR) {
+        // U rows per step.  Software pipelined: the loads of the next U rows are
+        // issued before the current U rows are interpolated, so every wave keeps
+        // up to 2U wide loads in flight while it works.  Per row only the
+        // element offset, the outer-table index and the coordinate on axis D-2
+        // are kept; the weights are formed when the row is processed.
+        constexpr int U = V >= 8 ? 2 : 4;
+        auto prep_load = [&](int64_t rw, int64_t (&of)[U], int (&oi)[U], int (&xi)[U], bool (&okk)[U],
+                             float (&fl)[U][V]) {
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                okk[u] = rw + (int64_t)u * rpi < r1;
+                oi[u] = okk[u] ? (int)(o - o0) : 0;
+                const int xin = rs.in_lo + r;
+                xi[u] = xin;
+                of[u] = otab[oi[u]].off + (int64_t)xin * rs.in_stride + xoff;
+                r += sr;
+                o += so;
+                if (r >= rs.in_len) {
+                    r -= rs.in_len;
+                    o += 1;
+                }
+            }
+    #pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (okk[u]) load_chunk<Tin, V>(in + of[u], fl[u]);
+        };
+        auto process = [&](const int64_t (&offs)[U], const int (&oi)[U], const int (&xi)[U], const bool (&ok)[U],
+                           const float (&fl)[U][V]) {
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) break;
+                float rc[NO];
+                if constexpr (D == 1) {
+                    rc[0] = 1.0f;
+                } else {
+                    const OT &te = otab[oi[u]];
+                    const float w = cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xi[u]);
+                    const float omw = 1.0f - w;
+    #pragma unroll
+                    for (int q = 0; q < NOH; ++q) {
+                        const float cq = D >= 3 ? te.coef[q] : 1.0f;
+                        rc[2 * q] = cq * omw;
+                        rc[2 * q + 1] = cq * w;
+                    }
+                }
+                float y[V];
+    #pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const float fe = fl[u][e];
+                    float Lv[NC];
+                    if constexpr (AHR) {
+    #pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            Lv[c] = lut[__umul24(c, nb) + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
+                    } else {
+                        const int b = bin_of(fe, glo, gsc, nbf, nbm1);
+                        const float *p = lut + __umul24(b, SB) + lbase[e];
+                        if constexpr (NO % 4 == 0) {
+    #pragma unroll
+                            for (int c = 0; c < NC; c += 4) {
+                                const float4 q = *reinterpret_cast<const float4 *>(p + c);
+                                Lv[c] = q.x;
+                                Lv[c + 1] = q.y;
+                                Lv[c + 2] = q.z;
+                                Lv[c + 3] = q.w;
+                            }
+                        } else if constexpr (NO % 2 == 0) {
+    #pragma unroll
+                            for (int c = 0; c < NC; c += 2) {
+                                const float2 q = *reinterpret_cast<const float2 *>(p + c);
+                                Lv[c] = q.x;
+                                Lv[c + 1] = q.y;
+                            }
+                        } else {
+    #pragma unroll
+                            for (int c = 0; c < NC; ++c) Lv[c] = p[c];
+                        }
+                    }
+                    float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
+    #pragma unroll
+                    for (int c = 1; c < NO; ++c) {
+                        A = __fmaf_rn(rc[c], Lv[c], A);
+                        B = __fmaf_rn(rc[c], Lv[NO + c], B);
+                    }
+                    y[e] = __fmaf_rn(wl[e], B - A, A);
+                }
+                const int64_t off = offs[u];
+                if (vecst) {
+                    // streaming stores when the unit writes whole cache lines;
+                    // otherwise write-back stores let L2 merge the parts of a
+                    // line that neighbouring units write
+                    if constexpr (V % 4 == 0) {
+                        f4 *op = (f4 *)((float *)d.out + off);
+                        if (d.ntst) {
+    #pragma unroll
+                            for (int q = 0; q < V / 4; ++q) {
+                                f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                                __builtin_nontemporal_store(t, op + q);
+                            }
+                        } else {
+    #pragma unroll
+                            for (int q = 0; q < V / 4; ++q) op[q] = f4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                        }
+                    }
+                } else {
+    #pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
+                }
+            }
+        };
+        int64_t ofA[U], ofB[U];
+        int oiA[U], oiB[U], xiA[U], xiB[U];
+        bool okA[U], okB[U];
+        float fA[U][V], fB[U][V];
+        const int64_t step = (int64_t)U * rpi;
+        int64_t row = rstart;
+        if (row < r1) {
+            prep_load(row, ofA, oiA, xiA, okA, fA);
+            for (;;) {
+                const int64_t nb = row + step;
+                if (nb < r1) prep_load(nb, ofB, oiB, xiB, okB, fB);
+                process(ofA, oiA, xiA, okA, fA);
+                row = nb;
+                if (row >= r1) break;
+                const int64_t na = row + step;
+                if (na < r1) prep_load(na, ofA, oiA, xiA, okA, fA);
+                process(ofB, oiB, xiB, okB, fB);
+                row = na;
+                if (row >= r1) break;
             }
         }
-        float fu[U][V];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (!ok[u]) break;
-            float rc[NO];
-            if constexpr (D == 1) {
-                rc[0] = 1.0f;
-            } else {
-                const float w = win[u];
-                const float omw = 1.0f - w;
-#pragma unroll
-                for (int q = 0; q < NOH; ++q) {
-                    rc[2 * q] = cfu[u][q] * omw;
-                    rc[2 * q + 1] = cfu[u][q] * w;
+    } else {
+        // rows whose loads are in flight together (with NT threads and two
+        // units per CU this keeps ~64 KiB of loads in flight per CU)
+        constexpr int U = V >= 8 ? 2 : 4;
+        for (int64_t row = rstart; row < r1; row += (int64_t)U * rpi) {
+            int64_t offs[U];
+            float win[U];
+            float cfu[U][NOH];
+            bool ok[U];
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ok[u] = row + (int64_t)u * rpi < r1;
+                const OT &te = otab[ok[u] ? (int)(o - o0) : 0];
+                const int xin = rs.in_lo + r;
+                offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
+                win[u] = D >= 2 ? cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xin) : 0.f;
+    #pragma unroll
+                for (int q = 0; q < NOH; ++q) cfu[u][q] = D >= 3 ? te.coef[q] : 1.0f;
+                r += sr;
+                o += so;
+                if (r >= rs.in_len) {
+                    r -= rs.in_len;
+                    o += 1;
                 }
             }
-            float y[V];
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float fe = fu[u][e];
-                float Lv[NC];
-                if constexpr (AHR) {
-#pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        Lv[c] = lut[__umul24(c, nb) + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
+            float fu[U][V];
+    #pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) break;
+                float rc[NO];
+                if constexpr (D == 1) {
+                    rc[0] = 1.0f;
                 } else {
-                    const int b = bin_of(fe, glo, gsc, nbf, nbm1);
-                    const float *p = lut + __umul24(b, SB) + lbase[e];
-                    if constexpr (NO % 4 == 0) {
-#pragma unroll
-                        for (int c = 0; c < NC; c += 4) {
-                            const float4 q = *reinterpret_cast<const float4 *>(p + c);
-                            Lv[c] = q.x;
-                            Lv[c + 1] = q.y;
-                            Lv[c + 2] = q.z;
-                            Lv[c + 3] = q.w;
-                        }
-                    } else if constexpr (NO % 2 == 0) {
-#pragma unroll
-                        for (int c = 0; c < NC; c += 2) {
-                            const float2 q = *reinterpret_cast<const float2 *>(p + c);
-                            Lv[c] = q.x;
-                            Lv[c + 1] = q.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) Lv[c] = p[c];
+                    const float w = win[u];
+                    const float omw = 1.0f - w;
+    #pragma unroll
+                    for (int q = 0; q < NOH; ++q) {
+                        rc[2 * q] = cfu[u][q] * omw;
+                        rc[2 * q + 1] = cfu[u][q] * w;
                     }
                 }
-                float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
-#pragma unroll
-                for (int c = 1; c < NO; ++c) {
-                    A = __fmaf_rn(rc[c], Lv[c], A);
-                    B = __fmaf_rn(rc[c], Lv[NO + c], B);
-                }
-                y[e] = __fmaf_rn(wl[e], B - A, A);
-            }
-            const int64_t off = offs[u];
-            if (vecst) {
-                // streaming stores when the unit writes whole cache lines;
-                // otherwise write-back stores let L2 merge the parts of a
-                // line that neighbouring units write
-                if constexpr (V % 4 == 0) {
-                    f4 *op = (f4 *)((float *)d.out + off);
-                    if (d.ntst) {
-#pragma unroll
-                        for (int q = 0; q < V / 4; ++q) {
-                            f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
-                            __builtin_nontemporal_store(t, op + q);
-                        }
+                float y[V];
+    #pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const float fe = fu[u][e];
+                    float Lv[NC];
+                    if constexpr (AHR) {
+    #pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            Lv[c] = lut[__umul24(c, nb) + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
                     } else {
-#pragma unroll
-                        for (int q = 0; q < V / 4; ++q) op[q] = f4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                        const int b = bin_of(fe, glo, gsc, nbf, nbm1);
+                        const float *p = lut + __umul24(b, SB) + lbase[e];
+                        if constexpr (NO % 4 == 0) {
+    #pragma unroll
+                            for (int c = 0; c < NC; c += 4) {
+                                const float4 q = *reinterpret_cast<const float4 *>(p + c);
+                                Lv[c] = q.x;
+                                Lv[c + 1] = q.y;
+                                Lv[c + 2] = q.z;
+                                Lv[c + 3] = q.w;
+                            }
+                        } else if constexpr (NO % 2 == 0) {
+    #pragma unroll
+                            for (int c = 0; c < NC; c += 2) {
+                                const float2 q = *reinterpret_cast<const float2 *>(p + c);
+                                Lv[c] = q.x;
+                                Lv[c + 1] = q.y;
+                            }
+                        } else {
+    #pragma unroll
+                            for (int c = 0; c < NC; ++c) Lv[c] = p[c];
+                        }
                     }
+                    float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
+    #pragma unroll
+                    for (int c = 1; c < NO; ++c) {
+                        A = __fmaf_rn(rc[c], Lv[c], A);
+                        B = __fmaf_rn(rc[c], Lv[NO + c], B);
+                    }
+                    y[e] = __fmaf_rn(wl[e], B - A, A);
                 }
-            } else {
-#pragma unroll
-                for (int e = 0; e < V; ++e)
-                    if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
+                const int64_t off = offs[u];
+                if (vecst) {
+                    // streaming stores when the unit writes whole cache lines;
+                    // otherwise write-back stores let L2 merge the parts of a
+                    // line that neighbouring units write
+                    if constexpr (V % 4 == 0) {
+                        f4 *op = (f4 *)((float *)d.out + off);
+                        if (d.ntst) {
+    #pragma unroll
+                            for (int q = 0; q < V / 4; ++q) {
+                                f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                                __builtin_nontemporal_store(t, op + q);
+                            }
+                        } else {
+    #pragma unroll
+                            for (int q = 0; q < V / 4; ++q) op[q] = f4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+                        }
+                    }
+                } else {
+    #pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
+                }
             }
         }
     }

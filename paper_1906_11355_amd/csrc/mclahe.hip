@@ -135,7 +135,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     const mclahe_tuning &t = p->tune;
 
     // ---- histogram units --------------------------------------------------
-    int R = t.hist_copies > 0 ? t.hist_copies : 2;   // 2 replicas: fastest measured on Poisson counts
+    int R = t.hist_copies > 0 ? t.hist_copies : 1;   // 1 replica: fastest measured on Poisson counts
     if (R != 1 && R != 2 && R != 4 && R != 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "hist_copies must be 1, 2, 4 or 8");
     const size_t hdr = hist_lds_header();
     while (R > 1 && hdr + (size_t)mc_hist_slot_stride(p->nb, R) * 4 > MC_LDS_BUDGET) R /= 2;
@@ -185,8 +185,6 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.hR = R;
     // hist_peel: 0 = default (no aggregation), k >= 1 = k - 1 rounds
     v.hPeel = t.hist_peel > 0 ? std::min(t.hist_peel - 1, 2) : 0;
-    // hist_hotbin: 0 = default (off), 1 = off, 2 = on
-    v.hHot = t.hist_hotbin == 2 ? 1 : 0;
     v.hCols = 1;
     int64_t omax_h = 1, rmax_h = 1;
     for (int i = 0; i < D - 1; ++i) {
@@ -631,8 +629,8 @@ static void tune_cache_load()
     if (!fp) return;
     char key[512];
     mclahe_tuning t;
-    while (fscanf(fp, "%511s %d %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
-                  &t.map_rows_split, &t.map_group, &t.hist_hotbin) == 7)
+    while (fscanf(fp, "%511s %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
+                  &t.map_rows_split, &t.map_group) == 6)
         g_tune_cache[key] = t;
     fclose(fp);
 }
@@ -644,8 +642,8 @@ static void tune_cache_store(const std::string &key, const mclahe_tuning &t)
     if (!f) return;
     FILE *fp = fopen(f, "a");
     if (!fp) return;
-    fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
-            t.map_rows_split, t.map_group, t.hist_hotbin);
+    fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
+            t.map_rows_split, t.map_group);
     fclose(fp);
 }
 
@@ -821,7 +819,6 @@ mclahe_status mclahe_plan_get_tuning(mclahe_plan_t p, mclahe_tuning *t)
     t->hist_peel = p->v.hPeel + 1;
     t->map_rows_split = p->v.mCr;
     t->map_group = p->v.mG;
-    t->hist_hotbin = p->v.hHot ? 2 : 1;
     return MCLAHE_SUCCESS;
 }
 
@@ -829,7 +826,7 @@ mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
 {
     if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
     if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->hist_peel < 0 ||
-        t->hist_peel > 3 || t->hist_hotbin < 0 || t->hist_hotbin > 2 || t->hist_copies < 0)
+        t->hist_peel > 3 || t->hist_copies < 0)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "tuning fields must be >= 0 (hist_peel <= 3)");
     const mclahe_tuning old = p->tune;
     p->tune = *t;
