@@ -113,10 +113,12 @@ typedef struct {
  *   hist_peel         : wavefront aggregation of colliding bins: 1 = off,
  *                       2 = one round, 3 = two rounds (0 = default)
  *   map_rows_split    : row chunks per cell column in the interpolation pass
- *   map_group         : interpolation cells per work unit along the last axis */
+ *   map_group         : interpolation cells per work unit along the last axis
+ *   map_unit_chunks   : row chunks an interpolation unit runs on one staging of
+ *                       its LUTs (1 .. map_rows_split)                        */
 typedef struct {
     int32_t hist_rows_split, hist_copies, hist_peel;
-    int32_t map_rows_split, map_group;
+    int32_t map_rows_split, map_group, map_unit_chunks;
 } mclahe_tuning;
 
 /* Create a plan (host only; no device call).  Arguments follow the paper's

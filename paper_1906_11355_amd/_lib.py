@@ -42,7 +42,7 @@ class Geometry(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("hist_rows_split", "hist_copies", "hist_peel",
-                                                "map_rows_split", "map_group")]
+                                                "map_rows_split", "map_group", "map_unit_chunks")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -132,8 +132,10 @@ struct McVol {
     // ---- interpolation work units -------------------------------------------
     int32_t mG, mS, mCr, mP;  // cells per group, segments on the last axis,
                               // row chunks, parts per cell (mP > 1: mG = 1)
+    int32_t mK, mU;           // row chunks per unit (on one LUT staging),
+                              // units per (cell column, segment) = ceil(mCr/mK)
     int64_t mCols;            // cell columns (prod of n_i - 1, i < D-1)
-    uint32_t n_map_wu;        // mCols * mS * mCr
+    uint32_t n_map_wu;        // mCols * mS * mU
     uint32_t n_clip_wu;       // = nker
     // ---- buffers -------------------------------------------------------------
     const void *in;

@@ -782,12 +782,12 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
 __device__ __forceinline__ uint32_t map_unit_order(const McVol &d, uint32_t u)
 {
     const uint32_t ns = (uint32_t)d.mS;
-    const uint32_t ncc = d.n_map_wu / ns;           // (cell column, chunk) pairs
+    const uint32_t ncc = d.n_map_wu / ns;           // (cell column, unit chunk) pairs
     if (ns == 1 || (ncc & 7u)) return u;
     const uint32_t x = u & 7u, k = u >> 3;
     const uint32_t g = k % ns, cc = (k / ns) * 8u + x;
-    const uint32_t col = cc / (uint32_t)d.mCr, chunk = cc - col * (uint32_t)d.mCr;
-    return (col * ns + g) * (uint32_t)d.mCr + chunk;
+    const uint32_t col = cc / (uint32_t)d.mU, chunk = cc - col * (uint32_t)d.mU;
+    return (col * ns + g) * (uint32_t)d.mU + chunk;
 }
 
 __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int &chunk, int &grp,
@@ -795,8 +795,8 @@ __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int
 {
     const int D = d.D;
     wu = map_unit_order(d, wu);
-    chunk = (int)(wu % (uint32_t)d.mCr);
-    const uint32_t t1 = wu / (uint32_t)d.mCr;
+    chunk = (int)(wu % (uint32_t)d.mU);      // unit chunk: row chunks [chunk*mK, +mK)
+    const uint32_t t1 = wu / (uint32_t)d.mU;
     grp = (int)(t1 % (uint32_t)d.mS);
     int64_t c = (int64_t)(t1 / (uint32_t)d.mS);
 #pragma unroll
@@ -918,45 +918,15 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
         for (int c = 0; c < NC; ++c) clo[c] = csc[c] = 0.f;
     }
 
-    // rows of this chunk and the outer-row table (offsets, partial weights)
-    const int64_t r0 = rs.rows * chunk / d.mCr, r1 = rs.rows * (chunk + 1) / d.mCr;
-    const int64_t o0 = r0 / rs.in_len;
-    const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
-    for (int j = threadIdx.x; j < ocnt; j += NT) {
-        int32_t x[MC_MAXD];
-        decode_outer(d, rs, o0 + j, x);
-        int64_t off = 0;
-        float cf[NOH];
-        cf[0] = 1.0f;
-        int n = 1;
-#pragma unroll
-        for (int i = 0; i < D - 2; ++i) {
-            off += (int64_t)x[i] * d.stride[i];
-            const float w = cell_weight(d.ax[i], cidx[i], x[i]);
-            const float omw = 1.0f - w;
-            // tensor product, axis i becomes the next lower-order bit
-#pragma unroll
-            for (int q = NOH - 1; q >= 0; --q) {
-                if (q < 2 * n) {
-                    const float base = cf[q >> 1];
-                    cf[q] = (q & 1) ? base * w : base * omw;
-                }
-            }
-            n *= 2;
-        }
-        otab[j].off = off;
-#pragma unroll
-        for (int q = 0; q < NOH; ++q) otab[j].coef[q] = cf[q];
-    }
-    __syncthreads();
-
+    // the LUTs (and AHR ranges) staged above are published by the first
+    // chunk's barrier below
+    if (xe <= xs) return;   // an empty split part (uniform over the work-group)
     // thread mapping along the last axis (a split cell part may be empty)
-    if (xe <= xs) return;
     const int c_lo = xs / V, c_hi = (xe + V - 1) / V;
     const int cpr = c_hi - c_lo;
     const int rpi = NT / cpr;
     const int tch = threadIdx.x % cpr, trow = threadIdx.x / cpr;
-    if (!(trow < rpi)) return;
+    const bool tact = trow < rpi;
     const int64_t xoff = (int64_t)(c_lo + tch) * V;
     int lbase[V];      // LDS offset of the voxel's last-axis kernel pair
     float wl[V];
@@ -979,148 +949,50 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const Tin *in = (const Tin *)d.in;
     const float nbf = (float)nb;
     const int nbm1 = nb - 1;
-    const int64_t rstart = r0 + trow;
-    int64_t o = rstart / rs.in_len;
-    int r = (int)(rstart - o * rs.in_len);
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
     const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
-    // global range: software pipelined (below); per-kernel range keeps 2^D
-    // ranges in registers, so it runs one batch of rows at a time (else)
-    if constexpr (!AHR) {
-        // U rows per step.  Software pipelined: the loads of the next U rows are
-        // issued before the current U rows are interpolated, so every wave keeps
-        // up to 2U wide loads in flight while it works.  Per row only the
-        // element offset, the outer-table index and the coordinate on axis D-2
-        // are kept; the weights are formed when the row is processed.
-        constexpr int U = V >= 8 ? 2 : 4;
-        auto prep_load = [&](int64_t rw, int64_t (&of)[U], int (&oi)[U], int (&xi)[U], bool (&okk)[U],
-                             float (&fl)[U][V]) {
-    #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                okk[u] = rw + (int64_t)u * rpi < r1;
-                oi[u] = okk[u] ? (int)(o - o0) : 0;
-                const int xin = rs.in_lo + r;
-                xi[u] = xin;
-                of[u] = otab[oi[u]].off + (int64_t)xin * rs.in_stride + xoff;
-                r += sr;
-                o += so;
-                if (r >= rs.in_len) {
-                    r -= rs.in_len;
-                    o += 1;
+    // the unit's row chunks, one after another on the same staged LUTs; the
+    // outer-row table is rebuilt for each chunk
+    // (per-kernel range: one chunk per unit, which keeps its 2^D ranges in
+    // registers without spilling)
+    const int chA = chunk * d.mK, chB = AHR ? chA + 1 : mc_min(chA + d.mK, d.mCr);
+    for (int ch = chA; ch < chB; ++ch) {
+        const int64_t r0 = rs.rows * ch / d.mCr, r1 = rs.rows * (ch + 1) / d.mCr;
+        const int64_t o0 = r0 / rs.in_len;
+        const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
+        if (ch > chA) __syncthreads();   // every reader of the previous table is done
+        for (int j = threadIdx.x; j < ocnt; j += NT) {
+            int32_t x[MC_MAXD];
+            decode_outer(d, rs, o0 + j, x);
+            int64_t off = 0;
+            float cf[NOH];
+            cf[0] = 1.0f;
+            int n = 1;
+#pragma unroll
+            for (int i = 0; i < D - 2; ++i) {
+                off += (int64_t)x[i] * d.stride[i];
+                const float w = cell_weight(d.ax[i], cidx[i], x[i]);
+                const float omw = 1.0f - w;
+                // tensor product, axis i becomes the next lower-order bit
+#pragma unroll
+                for (int q = NOH - 1; q >= 0; --q) {
+                    if (q < 2 * n) {
+                        const float base = cf[q >> 1];
+                        cf[q] = (q & 1) ? base * w : base * omw;
+                    }
                 }
+                n *= 2;
             }
-    #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (okk[u]) load_chunk<Tin, V>(in + of[u], fl[u]);
-        };
-        auto process = [&](const int64_t (&offs)[U], const int (&oi)[U], const int (&xi)[U], const bool (&ok)[U],
-                           const float (&fl)[U][V]) {
-    #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (!ok[u]) break;
-                float rc[NO];
-                if constexpr (D == 1) {
-                    rc[0] = 1.0f;
-                } else {
-                    const OT &te = otab[oi[u]];
-                    const float w = cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xi[u]);
-                    const float omw = 1.0f - w;
-    #pragma unroll
-                    for (int q = 0; q < NOH; ++q) {
-                        const float cq = D >= 3 ? te.coef[q] : 1.0f;
-                        rc[2 * q] = cq * omw;
-                        rc[2 * q + 1] = cq * w;
-                    }
-                }
-                float y[V];
-    #pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    const float fe = fl[u][e];
-                    float Lv[NC];
-                    if constexpr (AHR) {
-    #pragma unroll
-                        for (int c = 0; c < NC; ++c)
-                            Lv[c] = lut[__umul24(c, nb) + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
-                    } else {
-                        const int b = bin_of(fe, glo, gsc, nbf, nbm1);
-                        const float *p = lut + __umul24(b, SB) + lbase[e];
-                        if constexpr (NO % 4 == 0) {
-    #pragma unroll
-                            for (int c = 0; c < NC; c += 4) {
-                                const float4 q = *reinterpret_cast<const float4 *>(p + c);
-                                Lv[c] = q.x;
-                                Lv[c + 1] = q.y;
-                                Lv[c + 2] = q.z;
-                                Lv[c + 3] = q.w;
-                            }
-                        } else if constexpr (NO % 2 == 0) {
-    #pragma unroll
-                            for (int c = 0; c < NC; c += 2) {
-                                const float2 q = *reinterpret_cast<const float2 *>(p + c);
-                                Lv[c] = q.x;
-                                Lv[c + 1] = q.y;
-                            }
-                        } else {
-    #pragma unroll
-                            for (int c = 0; c < NC; ++c) Lv[c] = p[c];
-                        }
-                    }
-                    float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
-    #pragma unroll
-                    for (int c = 1; c < NO; ++c) {
-                        A = __fmaf_rn(rc[c], Lv[c], A);
-                        B = __fmaf_rn(rc[c], Lv[NO + c], B);
-                    }
-                    y[e] = __fmaf_rn(wl[e], B - A, A);
-                }
-                const int64_t off = offs[u];
-                if (vecst) {
-                    // streaming stores when the unit writes whole cache lines;
-                    // otherwise write-back stores let L2 merge the parts of a
-                    // line that neighbouring units write
-                    if constexpr (V % 4 == 0) {
-                        f4 *op = (f4 *)((float *)d.out + off);
-                        if (d.ntst) {
-    #pragma unroll
-                            for (int q = 0; q < V / 4; ++q) {
-                                f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
-                                __builtin_nontemporal_store(t, op + q);
-                            }
-                        } else {
-    #pragma unroll
-                            for (int q = 0; q < V / 4; ++q) op[q] = f4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
-                        }
-                    }
-                } else {
-    #pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
-                }
-            }
-        };
-        int64_t ofA[U], ofB[U];
-        int oiA[U], oiB[U], xiA[U], xiB[U];
-        bool okA[U], okB[U];
-        float fA[U][V], fB[U][V];
-        const int64_t step = (int64_t)U * rpi;
-        int64_t row = rstart;
-        if (row < r1) {
-            prep_load(row, ofA, oiA, xiA, okA, fA);
-            for (;;) {
-                const int64_t nb = row + step;
-                if (nb < r1) prep_load(nb, ofB, oiB, xiB, okB, fB);
-                process(ofA, oiA, xiA, okA, fA);
-                row = nb;
-                if (row >= r1) break;
-                const int64_t na = row + step;
-                if (na < r1) prep_load(na, ofA, oiA, xiA, okA, fA);
-                process(ofB, oiB, xiB, okB, fB);
-                row = na;
-                if (row >= r1) break;
-            }
+            otab[j].off = off;
+#pragma unroll
+            for (int q = 0; q < NOH; ++q) otab[j].coef[q] = cf[q];
         }
-    } else {
+        __syncthreads();
+        if (!tact) continue;
+        const int64_t rstart = r0 + trow;
+        int64_t o = rstart / rs.in_len;
+        int r = (int)(rstart - o * rs.in_len);
         // rows whose loads are in flight together (with NT threads and two
         // units per CU this keeps ~64 KiB of loads in flight per CU)
         constexpr int U = V >= 8 ? 2 : 4;
@@ -1129,14 +1001,14 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             float win[U];
             float cfu[U][NOH];
             bool ok[U];
-    #pragma unroll
+#pragma unroll
             for (int u = 0; u < U; ++u) {
                 ok[u] = row + (int64_t)u * rpi < r1;
                 const OT &te = otab[ok[u] ? (int)(o - o0) : 0];
                 const int xin = rs.in_lo + r;
                 offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
                 win[u] = D >= 2 ? cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xin) : 0.f;
-    #pragma unroll
+#pragma unroll
                 for (int q = 0; q < NOH; ++q) cfu[u][q] = D >= 3 ? te.coef[q] : 1.0f;
                 r += sr;
                 o += so;
@@ -1146,10 +1018,10 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                 }
             }
             float fu[U][V];
-    #pragma unroll
+#pragma unroll
             for (int u = 0; u < U; ++u)
                 if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
-    #pragma unroll
+#pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!ok[u]) break;
                 float rc[NO];
@@ -1158,26 +1030,26 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                 } else {
                     const float w = win[u];
                     const float omw = 1.0f - w;
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < NOH; ++q) {
                         rc[2 * q] = cfu[u][q] * omw;
                         rc[2 * q + 1] = cfu[u][q] * w;
                     }
                 }
                 float y[V];
-    #pragma unroll
+#pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const float fe = fu[u][e];
                     float Lv[NC];
                     if constexpr (AHR) {
-    #pragma unroll
+#pragma unroll
                         for (int c = 0; c < NC; ++c)
                             Lv[c] = lut[__umul24(c, nb) + bin_of(fe, clo[c], csc[c], nbf, nbm1)];
                     } else {
                         const int b = bin_of(fe, glo, gsc, nbf, nbm1);
                         const float *p = lut + __umul24(b, SB) + lbase[e];
                         if constexpr (NO % 4 == 0) {
-    #pragma unroll
+#pragma unroll
                             for (int c = 0; c < NC; c += 4) {
                                 const float4 q = *reinterpret_cast<const float4 *>(p + c);
                                 Lv[c] = q.x;
@@ -1186,19 +1058,19 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                                 Lv[c + 3] = q.w;
                             }
                         } else if constexpr (NO % 2 == 0) {
-    #pragma unroll
+#pragma unroll
                             for (int c = 0; c < NC; c += 2) {
                                 const float2 q = *reinterpret_cast<const float2 *>(p + c);
                                 Lv[c] = q.x;
                                 Lv[c + 1] = q.y;
                             }
                         } else {
-    #pragma unroll
+#pragma unroll
                             for (int c = 0; c < NC; ++c) Lv[c] = p[c];
                         }
                     }
                     float A = rc[0] * Lv[0], B = rc[0] * Lv[NO];
-    #pragma unroll
+#pragma unroll
                     for (int c = 1; c < NO; ++c) {
                         A = __fmaf_rn(rc[c], Lv[c], A);
                         B = __fmaf_rn(rc[c], Lv[NO + c], B);
@@ -1213,18 +1085,18 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                     if constexpr (V % 4 == 0) {
                         f4 *op = (f4 *)((float *)d.out + off);
                         if (d.ntst) {
-    #pragma unroll
+#pragma unroll
                             for (int q = 0; q < V / 4; ++q) {
                                 f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
                                 __builtin_nontemporal_store(t, op + q);
                             }
                         } else {
-    #pragma unroll
+#pragma unroll
                             for (int q = 0; q < V / 4; ++q) op[q] = f4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
                         }
                     }
                 } else {
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < V; ++e)
                         if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
                 }

@@ -278,12 +278,30 @@ static mclahe_status derive(mclahe_plan_s *p)
         if (i <= D - 3) omax_m *= p->ax[i].b;
     }
     const int64_t crmin_m = fast ? std::max<int64_t>(1, (omax_m + MC_OMAX - 5) / (MC_OMAX - 4)) : 1;
-    int64_t mcr = t.map_rows_split > 0 ? t.map_rows_split
-                                       : (2048 + v.mCols * v.mS - 1) / (v.mCols * v.mS);
+    // default row split: enough chunks for ~2048 units; under a global range
+    // (where a unit runs several chunks on one LUT staging) also chunks of at
+    // most ~800 rows, the fastest measured at the 4D workload
+    int64_t mcr = (2048 + v.mCols * v.mS - 1) / (v.mCols * v.mS);
+    if (fast && p->mode == MC_GHR) mcr = std::max<int64_t>(mcr, (rmax_m + 799) / 800);
+    if (t.map_rows_split > 0) mcr = t.map_rows_split;
     mcr = std::max<int64_t>(mcr, crmin_m);
     mcr = std::min<int64_t>(mcr, std::max<int64_t>(rmax_m, crmin_m));
     v.mCr = (int)mcr;
-    const int64_t nmu = v.mCols * v.mS * v.mCr;
+    // row chunks per unit: each unit stages its LUTs once for mK chunks.
+    // Default: as many as keep >= 1024 units (four per CU).
+    int mk = 1;
+    if (fast && p->mode == MC_GHR) {
+        if (t.map_unit_chunks > 0) {
+            mk = t.map_unit_chunks;
+        } else {
+            const int64_t want_u = std::max<int64_t>(1, (1024 + v.mCols * v.mS - 1) / (v.mCols * v.mS));
+            mk = (int)((mcr + want_u - 1) / want_u);
+        }
+        mk = std::max(1, std::min(mk, v.mCr));
+    }
+    v.mK = mk;
+    v.mU = (v.mCr + mk - 1) / mk;
+    const int64_t nmu = v.mCols * v.mS * v.mU;
     if (nmu >= (int64_t)1 << 31) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "too many map units");
     v.n_map_wu = (uint32_t)nmu;
 
@@ -629,8 +647,8 @@ static void tune_cache_load()
     if (!fp) return;
     char key[512];
     mclahe_tuning t;
-    while (fscanf(fp, "%511s %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
-                  &t.map_rows_split, &t.map_group) == 6)
+    while (fscanf(fp, "%511s %d %d %d %d %d %d", key, &t.hist_rows_split, &t.hist_copies, &t.hist_peel,
+                  &t.map_rows_split, &t.map_group, &t.map_unit_chunks) == 7)
         g_tune_cache[key] = t;
     fclose(fp);
 }
@@ -642,8 +660,8 @@ static void tune_cache_store(const std::string &key, const mclahe_tuning &t)
     if (!f) return;
     FILE *fp = fopen(f, "a");
     if (!fp) return;
-    fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
-            t.map_rows_split, t.map_group);
+    fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), t.hist_rows_split, t.hist_copies, t.hist_peel,
+            t.map_rows_split, t.map_group, t.map_unit_chunks);
     fclose(fp);
 }
 
@@ -818,6 +836,7 @@ mclahe_status mclahe_plan_get_tuning(mclahe_plan_t p, mclahe_tuning *t)
     t->hist_copies = p->v.hR;
     t->hist_peel = p->v.hPeel + 1;
     t->map_rows_split = p->v.mCr;
+    t->map_unit_chunks = p->v.mK;
     t->map_group = p->v.mG;
     return MCLAHE_SUCCESS;
 }
@@ -825,7 +844,8 @@ mclahe_status mclahe_plan_get_tuning(mclahe_plan_t p, mclahe_tuning *t)
 mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
 {
     if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
-    if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->hist_peel < 0 ||
+    if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->map_unit_chunks < 0 ||
+        t->hist_peel < 0 ||
         t->hist_peel > 3 || t->hist_copies < 0)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "tuning fields must be >= 0 (hist_peel <= 3)");
     const mclahe_tuning old = p->tune;
@@ -1203,19 +1223,22 @@ mclahe_status mclahe_autotune(mclahe_plan_t p, const void *d_in, void *d_out, vo
     p->tune = best_t;
     derive(p);
     const int ncl = p->ax[p->D - 1].n - 1;
+    const int mcr0 = p->v.mCr;       // row split of the best histogram setting
     std::vector<int> groups = {1, 2, 4, ncl};
     for (int g : groups) {
         if (g < 1 || g > ncl) continue;
-        for (int f : {1, 2, 4}) {
-            mclahe_tuning t = best_t;
-            t.map_group = g;
-            t.map_rows_split = std::max(1, p->v.mCr * f / 2);
-            float ms;
-            if (time_cfg(t, ms) == MCLAHE_SUCCESS && ms < best_ms) {
-                best_ms = ms;
-                best_t = t;
+        for (int f : {1, 2, 4})
+            for (int k : {0, 1, 2, 1 << 20}) {   // unit chunks: default, 1, 2, all
+                mclahe_tuning t = best_t;
+                t.map_group = g;
+                t.map_rows_split = std::max(1, mcr0 * f / 2);
+                t.map_unit_chunks = k == (1 << 20) ? t.map_rows_split : k;
+                float ms;
+                if (time_cfg(t, ms) == MCLAHE_SUCCESS && ms < best_ms) {
+                    best_ms = ms;
+                    best_t = t;
+                }
             }
-        }
     }
     p->tune = best_t;
     derive(p);

@@ -102,6 +102,13 @@ def test_workspace_layout_and_tuning():
     t2 = p.tuning()
     assert t2["hist_rows_split"] == t["hist_rows_split"] * 2 and t2["hist_copies"] == 4
     assert t2["hist_peel"] == 1 and t2["map_group"] == 1 and t2["map_rows_split"] == 7
+    assert 1 <= t2["map_unit_chunks"] <= 7
+    p.set_tuning(**dict(t2, map_unit_chunks=3))
+    assert p.tuning()["map_unit_chunks"] == 3
+    p.set_tuning(**dict(t2, map_unit_chunks=99))          # clamped to the row split
+    assert p.tuning()["map_unit_chunks"] == 7
+    p.set_tuning(**t2)
+    t2 = p.tuning()
     # a split too coarse for the per-unit row table is raised to the minimum
     q = Plan((256, 256, 128, 32), (32, 32, 16, 8), 512, 0.02)
     q.set_tuning(map_rows_split=1, hist_rows_split=1)

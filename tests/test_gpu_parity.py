@@ -118,7 +118,9 @@ def test_in_place():
     dict(hist_copies=1, hist_peel=1), dict(hist_copies=4, hist_peel=3, hist_rows_split=1),
     dict(hist_copies=8, hist_peel=2, hist_rows_split=37), dict(map_group=1, map_rows_split=1),
     dict(map_group=3, map_rows_split=11), dict(hist_copies=2, map_group=2, map_rows_split=64),
-    dict(hist_peel=2, hist_copies=4), dict(hist_peel=3, hist_copies=1)])
+    dict(hist_peel=2, hist_copies=4), dict(hist_peel=3, hist_copies=1),
+    dict(map_rows_split=7, map_unit_chunks=1), dict(map_rows_split=7, map_unit_chunks=3),
+    dict(map_rows_split=7, map_unit_chunks=7, map_group=1)])
 def test_tuning_does_not_change_bits(tuning):
     rng = np.random.default_rng(7)
     x = rng.poisson(2.0, size=(40, 36, 30, 16)).astype(np.float32)
