@@ -108,36 +108,54 @@ __device__ __forceinline__ void store_elem(void *out, int dt, int64_t i, float y
     }
 }
 
-// Block-wide reductions over MC_T threads through LDS scratch of MC_T words.
+// Block-wide sum and exclusive scan over MC_T threads: wave-level shuffles
+// within each wave64, then one pass over the per-wave totals in LDS scratch
+// (at least MC_T / 64 words).  Integer sums: exact in any order.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
 __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
                                                             unsigned long long *s)
 {
-    s[threadIdx.x] = v;
+    constexpr int NW = MC_T / 64;
+    v = wave_sum_u64(v);
+    if (lane_id() == 0) s[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = MC_T / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    const unsigned long long r = s[0];
+    unsigned long long r = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) r += s[w];
     __syncthreads();
     return r;
 }
 
-// Exclusive prefix sum over the block (Hillis-Steele in LDS).
 __device__ __forceinline__ unsigned long long block_exscan_u64(unsigned long long v,
                                                                unsigned long long *s)
 {
-    s[threadIdx.x] = v;
+    constexpr int NW = MC_T / 64;
+    const int w = threadIdx.x >> 6;
+    const unsigned long long inc = wave_incl_scan_u64(v);
+    if (lane_id() == 63) s[w] = inc;
     __syncthreads();
-    for (int o = 1; o < MC_T; o <<= 1) {
-        const unsigned long long a = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0ull;
-        __syncthreads();
-        s[threadIdx.x] += a;
-        __syncthreads();
-    }
-    const unsigned long long r = s[threadIdx.x] - v;
+    unsigned long long off = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) off += q < w ? s[q] : 0ull;
     __syncthreads();
-    return r;
+    return off + inc - v;
 }
 
 // ----------------------------------------------------------- row iteration --
