@@ -219,6 +219,26 @@ mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans,
                                    void *d_workspace, void *host_image,
                                    size_t image_bytes, size_t *needed);
 
+/* Out-of-core run (the paper's Sec. V outlook: chunked processing of data
+ * that do not fit in memory).  Input and output stay in HOST memory
+ * (C-contiguous; pinned memory lets the copies run asynchronously; they must
+ * not alias); the volume passes through the device workspace in slabs of
+ * slab_layers kernel layers along axis 0 (rows of whole padded kernels).  A
+ * global range is one streamed min/max pass over all slabs first; then each
+ * slab is uploaded, histogrammed, clipped and turned into LUTs, and the
+ * interpolation cells whose two kernel layers are ready are mapped, keeping
+ * the last LUT layer of the previous slab as a one-layer halo; the output
+ * rows go back to the host.  The result is bit-identical to mclahe_run.
+ * Needs ndim >= 2.  The workspace (device, 256-byte aligned) holds one slab
+ * of input and output rows, the slab's histograms and LUTs plus the halo:
+ * mclahe_chunked_workspace_size().  Asynchronous on hip_stream like
+ * mclahe_run; host buffers must stay valid until the stream is done.
+ * Errors: NOT_SUPPORTED for ndim < 2, INVALID_VALUE for slab_layers < 1,
+ * NULL or aliasing buffers, WORKSPACE for a small or misaligned workspace. */
+mclahe_status mclahe_chunked_workspace_size(mclahe_plan_t plan, int slab_layers, size_t *bytes);
+mclahe_status mclahe_run_chunked(mclahe_plan_t plan, const void *h_in, void *h_out, int slab_layers,
+                                 void *d_workspace, size_t workspace_bytes, void *hip_stream);
+
 /* Autotune the plan's work decomposition on the current device: times the
  * candidate settings on the given buffers (which it overwrites) and keeps
  * the fastest.  Needs workspace_bytes >= mclahe_autotune_workspace_size().

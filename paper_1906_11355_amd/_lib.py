@@ -81,6 +81,8 @@ def _load():
                                      ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t), P, ctypes.c_size_t, P],
         "mclahe_batched_table": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
                                  P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_chunked_workspace_size": [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_run_chunked": [P, P, P, ctypes.c_int, P, ctypes.c_size_t, P],
         "mclahe_autotune_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_autotune": [P, P, P, P, ctypes.c_size_t, P],
         "mclahe_timer_create": [ctypes.POINTER(P), ctypes.c_int],
@@ -199,6 +201,16 @@ class Plan:
     # ---- device calls (pointers are integers; stream is a hipStream_t) ----
     def run_ptr(self, d_in: int, d_out: int, d_ws: int, ws_bytes: int, stream: int = 0):
         _check(lib.mclahe_run(self._h, d_in, d_out, d_ws, ws_bytes, stream))
+
+    def chunked_workspace_size(self, slab_layers: int) -> int:
+        n = ctypes.c_size_t()
+        _check(lib.mclahe_chunked_workspace_size(self._h, int(slab_layers), ctypes.byref(n)))
+        return n.value
+
+    def run_chunked_ptr(self, h_in: int, h_out: int, slab_layers: int, d_ws: int, ws_bytes: int,
+                        stream: int = 0):
+        """Out-of-core run: h_in / h_out are HOST pointers, d_ws a device workspace."""
+        _check(lib.mclahe_run_chunked(self._h, h_in, h_out, int(slab_layers), d_ws, ws_bytes, stream))
 
     def autotune_ptr(self, d_in: int, d_out: int, d_ws: int, ws_bytes: int, stream: int = 0):
         _check(lib.mclahe_autotune(self._h, d_in, d_out, d_ws, ws_bytes, stream))

@@ -124,6 +124,9 @@ struct McVol {
     int32_t hG, hP, hS, hCr;  // kernels per segment, parts per kernel,
                               // segments on the last axis, row chunks
     int32_t hR, hPeel;        // LDS replicas, aggregation rounds
+    int32_t wk0, wc0;         // window on axis 0 (chunked runs): first kernel
+                              // layer of the histogram units, first cell layer
+                              // of the interpolation units (0 for whole volumes)
     int32_t ntst;             // 1: output row segments are whole 64-byte blocks
                               //    -> streaming (non-temporal) stores
     int64_t hCols;            // kernel columns (prod of n_i, i < D-1)

@@ -252,7 +252,7 @@ __device__ __forceinline__ void hist_unit(const McVol &d, uint32_t wu, int64_t &
     for (int i = MC_MAXD - 2; i >= 0; --i) {
         if (i <= D - 2) {
             const int64_t q = c / d.ax[i].n;
-            const int k = (int)(c - q * d.ax[i].n);
+            const int k = (int)(c - q * d.ax[i].n) + (i == 0 ? d.wk0 : 0);
             c = q;
             obox[i] = mc_kernel_box(d.ax[i], k);
             rs.lo[i] = obox[i].lo;
@@ -822,7 +822,7 @@ __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int
         if (i <= D - 2) {
             const int nc = d.ax[i].n - 1;
             const int64_t q = c / nc;
-            cidx[i] = (int)(c - q * nc);
+            cidx[i] = (int)(c - q * nc) + (i == 0 ? d.wc0 : 0);
             c = q;
             int lo, hi;
             mc_cell_range(d.ax[i], cidx[i], lo, hi);

@@ -437,6 +437,226 @@ static mclahe_status run_plain(const mclahe_plan_s *p, const McVol &v, hipStream
     return MCLAHE_SUCCESS;
 }
 
+// ---------------------------------------------------------------- chunked --
+// Out-of-core runs: the volume stays in host memory and passes through the
+// device in slabs of whole kernel layers along axis 0 (the paper's outlook
+// on chunked processing of data that does not fit in memory).  Histograms,
+// clipping and LUTs of a kernel layer need only that layer's rows, so slab j
+// histograms kernel layers [kA, kB).  An interpolation cell straddles two
+// kernel layers, so slab j maps cell layers [kA - 1, kB - 1) with the LUTs of
+// layers [kA - 1, kB - 1]: the last LUT layer of slab j - 1 is kept as a
+// one-layer halo.  The global range (GHR) is one streamed min/max pass over
+// all slabs first; its partials stay on the device and every histogram unit
+// reduces them, exactly as in a whole-volume run.  Each launch runs the same
+// kernels on the same work units as mclahe_run, with axis-0 windows, so the
+// output is bit-identical.
+struct ChunkGeom {
+    int L = 0, n0 = 0;
+    std::vector<int> kA, kB, cA, cB;          // per slab: kernel and cell layers
+    std::vector<int64_t> hr0, hr1, mr0, mr1;  // per slab: rows read (hist, map)
+    std::vector<int64_t> rr0, rr1;            // range blocks (GHR)
+    std::vector<uint32_t> rparts;             // partials of each range block
+    uint32_t range_parts = 0;
+    int64_t row_elems = 1, layer_kernels = 1, cols_per_layer = 1, mcols_per_layer = 1;
+    int64_t max_rows = 0, max_out_rows = 0;
+    uint64_t o_in, o_out, o_part, o_rpart, o_hist, o_clipped, o_range, o_scale, o_lut, o_mrange, o_mscale,
+        total;
+};
+
+static uint32_t range_units(int64_t nvox)
+{
+    return (uint32_t)std::min<int64_t>(1024, std::max<int64_t>(1, nvox / (MC_T * 64)));
+}
+
+static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
+{
+    if (p->D < 2) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "chunked runs need at least 2 dimensions");
+    const McAxis &a0 = p->ax[0];
+    if (L < 1) return fail(MCLAHE_ERROR_INVALID_VALUE, "slab_layers must be >= 1");
+    L = std::min(L, a0.n);
+    g = ChunkGeom();
+    g.L = L;
+    g.n0 = a0.n;
+    for (int i = 1; i < p->D; ++i) {
+        g.row_elems *= p->shape[i];
+        g.layer_kernels *= p->ax[i].n;
+        if (i < p->D - 1) {
+            g.cols_per_layer *= p->ax[i].n;
+            g.mcols_per_layer *= p->ax[i].n - 1;
+        }
+    }
+    const int ns = (a0.n + L - 1) / L;
+    for (int j = 0; j < ns; ++j) {
+        const int kA = j * L, kB = std::min(kA + L, a0.n);
+        int64_t lo = INT64_MAX, hi = -1;
+        for (int k = kA; k < kB; ++k) {
+            const McBox b = mc_kernel_box(a0, k);
+            lo = std::min<int64_t>(lo, b.lo);
+            hi = std::max<int64_t>(hi, b.hi);
+        }
+        const int cA = j == 0 ? 0 : kA - 1, cB = j == ns - 1 ? a0.n - 1 : kB - 1;
+        int64_t mlo = 0, mhi = 0;
+        if (cB > cA) {
+            int l0, h0, l1, h1;
+            mc_cell_range(a0, cA, l0, h0);
+            mc_cell_range(a0, cB - 1, l1, h1);
+            mlo = l0;
+            mhi = h1;
+        }
+        g.kA.push_back(kA);
+        g.kB.push_back(kB);
+        g.cA.push_back(cA);
+        g.cB.push_back(cB);
+        g.hr0.push_back(lo);
+        g.hr1.push_back(hi);
+        g.mr0.push_back(mlo);
+        g.mr1.push_back(mhi);
+        g.max_rows = std::max(g.max_rows, std::max(hi - lo, mhi - mlo));
+        g.max_out_rows = std::max(g.max_out_rows, mhi - mlo);
+    }
+    if (p->mode == MC_GHR && !p->has_ur) {
+        for (int64_t r = 0; r < a0.s; r += g.max_rows) {
+            const int64_t r1 = std::min<int64_t>(a0.s, r + g.max_rows);
+            g.rr0.push_back(r);
+            g.rr1.push_back(r1);
+            const uint32_t u = range_units((r1 - r) * g.row_elems);
+            g.rparts.push_back(u);
+            g.range_parts += u;
+        }
+    }
+    const McVol &v = p->v;
+    const int64_t nhu = (int64_t)L * g.cols_per_layer * v.hS * v.hCr;
+    const int64_t nk = (int64_t)L * g.layer_kernels;
+    uint64_t o = 0;
+    g.o_in = o;
+    o = align256(o + (uint64_t)g.max_rows * g.row_elems * esize(p->in_dt));
+    g.o_out = o;
+    o = align256(o + (uint64_t)g.max_out_rows * g.row_elems * esize(p->out_dt));
+    g.o_part = o;
+    o = align256(o + (uint64_t)nhu * v.hG * p->nb * 4);
+    g.o_rpart = o;
+    o = align256(o + (p->mode == MC_GHR ? (uint64_t)std::max<uint32_t>(g.range_parts, 1) * 2
+                                        : (uint64_t)nhu * v.hG * 2) * 4);
+    g.o_hist = o;
+    o = align256(o + (uint64_t)nk * p->nb * 4);
+    g.o_clipped = o;
+    o = align256(o + (uint64_t)nk * p->nb * 8);
+    g.o_range = o;
+    o = align256(o + 2 * 4);
+    g.o_scale = o;
+    o = align256(o + 4);
+    g.o_lut = o;   // (L + 1) layers: the halo layer, then the slab's layers
+    o = align256(o + (uint64_t)(L + 1) * g.layer_kernels * p->nb * 4);
+    g.o_mrange = o;
+    g.o_mscale = o;
+    if (p->mode == MC_AHR) {
+        o = align256(o + (uint64_t)(L + 1) * g.layer_kernels * 2 * 4);
+        g.o_mscale = o;
+        o = align256(o + (uint64_t)(L + 1) * g.layer_kernels * 4);
+    }
+    g.total = o;
+    return MCLAHE_SUCCESS;
+}
+
+static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, const char *h_in, char *h_out,
+                                 char *ws, hipStream_t st)
+{
+    mclahe_status s;
+    const size_t es_in = esize(p->in_dt), es_out = esize(p->out_dt);
+    const size_t row_in = (size_t)g.row_elems * es_in, row_out = (size_t)g.row_elems * es_out;
+    char *inb = ws + g.o_in, *outb = ws + g.o_out;
+    const size_t layer_lut = (size_t)g.layer_kernels * p->nb;   // floats per LUT layer
+    float *lutb = (float *)(ws + g.o_lut);
+    float *mrange = (float *)(ws + g.o_mrange), *mscale = (float *)(ws + g.o_mscale);
+    const bool ahr = p->mode == MC_AHR;
+    size_t lds = 0;
+
+    // 1. global range: one streamed min/max pass (partials stay on the device)
+    uint32_t rp = 0;
+    for (size_t b = 0; b < g.rr0.size(); ++b) {
+        const int64_t rows = g.rr1[b] - g.rr0[b];
+        HIPCHK(hipMemcpyAsync(inb, h_in + (size_t)g.rr0[b] * row_in, (size_t)rows * row_in,
+                              hipMemcpyHostToDevice, st));
+        McVol v = p->v;
+        v.in = inb;
+        v.nvox = rows * g.row_elems;
+        v.n_range_wu = g.rparts[b];
+        v.rpart = (float *)(ws + g.o_rpart) + 2 * (size_t)rp;
+        if (v.vec > 1 && (v.nvox % v.vec)) v.vec = 1;
+        const KPair k = phase_kernels(p, v, 0, lds);
+        if ((s = launch(k.plain, v.n_range_wu, k.threads, lds, st, v))) return s;
+        rp += g.rparts[b];
+    }
+
+    // 2. slabs: histograms, clip/CDF/LUT, interpolation
+    for (size_t j = 0; j < g.kA.size(); ++j) {
+        const int kA = g.kA[j], kB = g.kB[j], nl = kB - kA;
+        if (j > 0) {
+            // the previous slab's last LUT layer becomes the halo layer 0
+            const int last = g.kB[j - 1] - g.kA[j - 1];
+            HIPCHK(hipMemcpyAsync(lutb, lutb + (size_t)last * layer_lut, layer_lut * 4,
+                                  hipMemcpyDeviceToDevice, st));
+            if (ahr) {
+                HIPCHK(hipMemcpyAsync(mrange, mrange + (size_t)last * g.layer_kernels * 2,
+                                      (size_t)g.layer_kernels * 2 * 4, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpyAsync(mscale, mscale + (size_t)last * g.layer_kernels,
+                                      (size_t)g.layer_kernels * 4, hipMemcpyDeviceToDevice, st));
+            }
+        }
+        const int64_t hrows = g.hr1[j] - g.hr0[j];
+        HIPCHK(hipMemcpyAsync(inb, h_in + (size_t)g.hr0[j] * row_in, (size_t)hrows * row_in,
+                              hipMemcpyHostToDevice, st));
+        McVol v = p->v;
+        v.wk0 = kA;
+        v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
+        v.n_clip_wu = (uint32_t)((int64_t)nl * g.layer_kernels);
+        v.n_range_wu = g.range_parts;
+        v.in = inb - (size_t)g.hr0[j] * row_in;      // global rows index the slab
+        v.out = nullptr;
+        v.part = (uint32_t *)(ws + g.o_part);
+        v.rpart = (float *)(ws + g.o_rpart);
+        v.hist = (uint32_t *)(ws + g.o_hist);
+        v.clipped = (unsigned long long *)(ws + g.o_clipped);
+        v.lut = lutb + layer_lut;                     // slab layers after the halo
+        if (ahr) {
+            v.range = mrange + (size_t)g.layer_kernels * 2;
+            v.scale = mscale + g.layer_kernels;
+        } else {
+            v.range = (float *)(ws + g.o_range);
+            v.scale = (float *)(ws + g.o_scale);
+        }
+        if (v.vec > 1 && ((uintptr_t)v.in % 16)) v.vec = 1;
+        for (int ph = 0; ph < 3; ++ph) {
+            const KPair k = phase_kernels(p, v, ph, lds);
+            if (ph == 0 && !ahr) continue;            // GHR range done above
+            if ((s = launch(k.plain, mc_phase_units(v, ph), k.threads, lds, st, v))) return s;
+        }
+        const int cA = g.cA[j], cB = g.cB[j];
+        if (cB <= cA) continue;
+        const int64_t mrows = g.mr1[j] - g.mr0[j];
+        HIPCHK(hipMemcpyAsync(inb, h_in + (size_t)g.mr0[j] * row_in, (size_t)mrows * row_in,
+                              hipMemcpyHostToDevice, st));
+        McVol m = v;
+        m.wc0 = cA;
+        m.n_map_wu = (uint32_t)((int64_t)(cB - cA) * g.mcols_per_layer * v.mS * v.mU);
+        m.in = inb - (size_t)g.mr0[j] * row_in;
+        m.out = outb - (size_t)g.mr0[j] * row_out;
+        // LUT layer 0 of the buffer is global kernel layer kA - 1
+        m.lut = lutb - (int64_t)(kA - 1) * (int64_t)layer_lut;
+        if (ahr) {
+            m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
+            m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
+        }
+        m.vec = p->v.vec;
+        if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.vec = 1;
+        const KPair k = phase_kernels(p, m, 3, lds);
+        if ((s = launch(k.plain, m.n_map_wu, k.threads, lds, st, m))) return s;
+        HIPCHK(hipMemcpyAsync(h_out + (size_t)g.mr0[j] * row_out, outb, (size_t)mrows * row_out,
+                              hipMemcpyDeviceToHost, st));
+    }
+    return MCLAHE_SUCCESS;
+}
+
 struct mclahe_timer_s {
     std::vector<hipEvent_t> ev;   // 5 per run
     int max_runs = 0, runs = 0;
@@ -1179,6 +1399,31 @@ mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans, const 
     fill_table(n, plans, d_in, d_out, (char *const *)d_ws, L, img);
     std::lock_guard<std::mutex> lk(g_graph_mu);      // the staging ring is shared
     return batched_direct(L, img, (char *)d_table, (hipStream_t)stream);
+}
+
+mclahe_status mclahe_chunked_workspace_size(mclahe_plan_t p, int slab_layers, size_t *bytes)
+{
+    if (!p || !bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    ChunkGeom g;
+    mclahe_status s = chunk_geom(p, slab_layers, g);
+    if (s) return s;
+    *bytes = g.total;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_chunked(mclahe_plan_t p, const void *h_in, void *h_out, int slab_layers, void *d_ws,
+                                 size_t wsb, void *stream)
+{
+    g_err.clear();
+    if (!p || !h_in || !h_out || !d_ws) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    if (h_in == h_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "chunked runs cannot work in place");
+    ChunkGeom g;
+    mclahe_status s = chunk_geom(p, slab_layers, g);
+    if (s) return s;
+    if ((uintptr_t)d_ws % 256) return fail(MCLAHE_ERROR_WORKSPACE, "workspace not 256-byte aligned");
+    if (wsb < g.total) return fail(MCLAHE_ERROR_WORKSPACE, "workspace too small: %zu < %zu bytes", wsb,
+                                   (size_t)g.total);
+    return run_chunked(p, g, (const char *)h_in, (char *)h_out, (char *)d_ws, (hipStream_t)stream);
 }
 
 mclahe_status mclahe_autotune_workspace_size(mclahe_plan_t p, size_t *bytes)

@@ -181,6 +181,30 @@ def test_batched_split_table_and_argument_checks():
         assert e.value.status == status, (kw, e.value)
 
 
+def test_chunked_sizes_and_argument_checks():
+    p = Plan((64, 48, 40), (16, 12, 10), 128, 0.02)
+    sizes = [p.chunked_workspace_size(L) for L in (1, 2, 3, 5, 50)]
+    assert sizes == sorted(sizes) and sizes[-2] == sizes[-1]       # clamped to the 5 kernel layers
+    assert sizes[0] < p.workspace_size() + 64 * 48 * 40 * 8         # a slab, not the volume
+    need = sizes[1]
+    for kw, status in [
+        (dict(L=0), _lib.INVALID_VALUE),
+        (dict(h_out=1 << 20), _lib.INVALID_VALUE),                 # in place
+        (dict(h_in=0), _lib.INVALID_VALUE),
+        (dict(ws=(4 << 20) + 8), _lib.WORKSPACE),
+        (dict(wsb=need - 1), _lib.WORKSPACE),
+    ]:
+        a = dict(h_in=1 << 20, h_out=2 << 20, L=2, ws=4 << 20, wsb=need)
+        a.update(kw)
+        with pytest.raises(MclaheError) as e:
+            p.run_chunked_ptr(a["h_in"], a["h_out"], a["L"], a["ws"], a["wsb"])
+        assert e.value.status == status, (kw, e.value)
+    q = Plan((1000,), (37,), 64, 0.1)
+    with pytest.raises(MclaheError) as e:
+        q.chunked_workspace_size(2)
+    assert e.value.status == _lib.NOT_SUPPORTED
+
+
 def test_plan_count_limits():
     with pytest.raises(MclaheError):
         Plan((2 ** 20, 2 ** 20), (2 ** 19, 2 ** 19), 16, 0.1)   # kernel voxels >= 2^32
