@@ -454,12 +454,13 @@ struct ChunkGeom {
     int L = 0, n0 = 0;
     std::vector<int> kA, kB, cA, cB;          // per slab: kernel and cell layers
     std::vector<int64_t> hr0, hr1, mr0, mr1;  // per slab: rows read (hist, map)
+    std::vector<int64_t> base;                // per slab: first row held in its buffer
     std::vector<int64_t> rr0, rr1;            // range blocks (GHR)
     std::vector<uint32_t> rparts;             // partials of each range block
     uint32_t range_parts = 0;
     int64_t row_elems = 1, layer_kernels = 1, cols_per_layer = 1, mcols_per_layer = 1;
     int64_t max_rows = 0, max_out_rows = 0;
-    uint64_t o_in, o_out, o_part, o_rpart, o_hist, o_clipped, o_range, o_scale, o_lut, o_mrange, o_mscale,
+    uint64_t o_in, o_in2, o_out, o_part, o_rpart, o_hist, o_clipped, o_range, o_scale, o_lut, o_mrange, o_mscale,
         total;
 };
 
@@ -511,7 +512,12 @@ static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
         g.hr1.push_back(hi);
         g.mr0.push_back(mlo);
         g.mr1.push_back(mhi);
-        g.max_rows = std::max(g.max_rows, std::max(hi - lo, mhi - mlo));
+        // the slab's buffer holds rows [min(mlo, lo), hi): the map's halo
+        // rows (the second half of the previous kernel layer) and the
+        // histogram rows; the map rows lie inside
+        const int64_t b0 = cB > cA ? std::min(mlo, lo) : lo;
+        g.base.push_back(b0);
+        g.max_rows = std::max(g.max_rows, hi - b0);
         g.max_out_rows = std::max(g.max_out_rows, mhi - mlo);
     }
     if (p->mode == MC_GHR && !p->has_ur) {
@@ -528,7 +534,9 @@ static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
     const int64_t nhu = (int64_t)L * g.cols_per_layer * v.hS * v.hCr;
     const int64_t nk = (int64_t)L * g.layer_kernels;
     uint64_t o = 0;
-    g.o_in = o;
+    g.o_in = o;   // two slab buffers, used alternately (halo rows pass from one to the next)
+    o = align256(o + (uint64_t)g.max_rows * g.row_elems * esize(p->in_dt));
+    g.o_in2 = o;
     o = align256(o + (uint64_t)g.max_rows * g.row_elems * esize(p->in_dt));
     g.o_out = o;
     o = align256(o + (uint64_t)g.max_out_rows * g.row_elems * esize(p->out_dt));
@@ -564,7 +572,8 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
     mclahe_status s;
     const size_t es_in = esize(p->in_dt), es_out = esize(p->out_dt);
     const size_t row_in = (size_t)g.row_elems * es_in, row_out = (size_t)g.row_elems * es_out;
-    char *inb = ws + g.o_in, *outb = ws + g.o_out;
+    char *inbuf[2] = {ws + g.o_in, ws + g.o_in2};
+    char *inb = inbuf[0], *outb = ws + g.o_out;
     const size_t layer_lut = (size_t)g.layer_kernels * p->nb;   // floats per LUT layer
     float *lutb = (float *)(ws + g.o_lut);
     float *mrange = (float *)(ws + g.o_mrange), *mscale = (float *)(ws + g.o_mscale);
@@ -603,15 +612,24 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
                                       (size_t)g.layer_kernels * 4, hipMemcpyDeviceToDevice, st));
             }
         }
+        // slab buffer: halo rows [base, hr0) from the previous slab's buffer
+        // (device to device), then the new rows [hr0, hr1) from the host
+        char *cur = inbuf[j & 1];
+        const int64_t base = g.base[j];
+        if (g.hr0[j] > base) {
+            const char *prev = inbuf[(j - 1) & 1];
+            HIPCHK(hipMemcpyAsync(cur, prev + (size_t)(base - g.base[j - 1]) * row_in,
+                                  (size_t)(g.hr0[j] - base) * row_in, hipMemcpyDeviceToDevice, st));
+        }
         const int64_t hrows = g.hr1[j] - g.hr0[j];
-        HIPCHK(hipMemcpyAsync(inb, h_in + (size_t)g.hr0[j] * row_in, (size_t)hrows * row_in,
-                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(cur + (size_t)(g.hr0[j] - base) * row_in, h_in + (size_t)g.hr0[j] * row_in,
+                              (size_t)hrows * row_in, hipMemcpyHostToDevice, st));
         McVol v = p->v;
         v.wk0 = kA;
         v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
         v.n_clip_wu = (uint32_t)((int64_t)nl * g.layer_kernels);
         v.n_range_wu = g.range_parts;
-        v.in = inb - (size_t)g.hr0[j] * row_in;      // global rows index the slab
+        v.in = cur - (size_t)base * row_in;           // global rows index the slab
         v.out = nullptr;
         v.part = (uint32_t *)(ws + g.o_part);
         v.rpart = (float *)(ws + g.o_rpart);
@@ -634,12 +652,10 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
         const int cA = g.cA[j], cB = g.cB[j];
         if (cB <= cA) continue;
         const int64_t mrows = g.mr1[j] - g.mr0[j];
-        HIPCHK(hipMemcpyAsync(inb, h_in + (size_t)g.mr0[j] * row_in, (size_t)mrows * row_in,
-                              hipMemcpyHostToDevice, st));
         McVol m = v;
         m.wc0 = cA;
         m.n_map_wu = (uint32_t)((int64_t)(cB - cA) * g.mcols_per_layer * v.mS * v.mU);
-        m.in = inb - (size_t)g.mr0[j] * row_in;
+        m.in = cur - (size_t)base * row_in;
         m.out = outb - (size_t)g.mr0[j] * row_out;
         // LUT layer 0 of the buffer is global kernel layer kA - 1
         m.lut = lutb - (int64_t)(kA - 1) * (int64_t)layer_lut;
