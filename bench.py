@@ -369,10 +369,32 @@ def bench_batched(torch, np, _lib, items, dev):
 
     ms_p, ms_b, ms_s = timeit(plain), timeit(batched), timeit(split)
     same = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c in zip(outs_b, outs_p, outs_s))
+    ref = [o.clone() for o in outs_p]
+    # autotune every plan (time reported separately), then time again; the
+    # batched workspace layout depends on the tuning, so it is re-sized
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for p, x, o in zip(plans, xs, outs_p):
+        w = torch.empty(p.autotune_workspace_size(), dtype=torch.uint8, device=dev)
+        p.autotune_ptr(x.data_ptr(), o.data_ptr(), w.data_ptr(), w.numel(), st)
+        del w
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t
+    wsb = torch.empty(_lib.batched_workspace_size(plans), dtype=torch.uint8, device=dev)
+    wsp = [torch.empty(p.workspace_size(), dtype=torch.uint8, device=dev) for p in plans]
+    ws_v = [torch.empty(p.workspace_size(), dtype=torch.uint8, device=dev) for p in plans]
+    tbl = torch.empty(_lib.batched_table_size(plans), dtype=torch.uint8, device=dev)
+    mt_p, mt_b, mt_s = timeit(plain), timeit(batched), timeit(split)
+    same_t = all(torch.equal(a, r) and torch.equal(b, r) and torch.equal(c, r)
+                 for a, b, c, r in zip(outs_p, outs_b, outs_s, ref))
     return {"volumes": len(xs), "voxels": vox, "plain_ms": round(ms_p, 3), "batched_ms": round(ms_b, 3),
             "split_direct_ms": round(ms_s, 3),
             "plain_Gvox_s": round(vox / ms_p / 1e6, 2), "batched_Gvox_s": round(vox / ms_b / 1e6, 2),
-            "bit_identical": bool(same)}
+            "bit_identical": bool(same),
+            "autotune_s": round(tune_s, 2),
+            "tuned": {"plain_ms": round(mt_p, 3), "batched_ms": round(mt_b, 3), "split_direct_ms": round(mt_s, 3),
+                      "batched_Gvox_s": round(vox / mt_b / 1e6, 2),
+                      "bit_identical_to_untuned": bool(same_t)}}
 
 
 def bench_serve(torch, np, items, dev, rates, budget_gib):

@@ -9,6 +9,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 import tempfile
 
 import numpy as np
@@ -203,6 +204,23 @@ def test_chunked_sizes_and_argument_checks():
     with pytest.raises(MclaheError) as e:
         q.chunked_workspace_size(2)
     assert e.value.status == _lib.NOT_SUPPORTED
+
+
+def test_tuning_cache_file_is_read_at_plan_creation(tmp_path):
+    """A cache line written by the autotuner is applied to new plans of the
+    same problem (fresh process: the file is read once per process)."""
+    cache = tmp_path / "tune.txt"
+    key = "D3_64x16_48x12_40x10_n128_m0_i2_o2_u0"
+    cache.write_text(f"{key} 7 4 2 9 1 3\n")
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1906_11355_amd._lib import Plan\n"
+            "print(Plan((64, 48, 40), (16, 12, 10), 128, 0.02).tuning())") % ROOT
+    env = dict(os.environ, MCLAHE_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stderr
+    t = eval(r.stdout.strip().splitlines()[-1])
+    assert (t["hist_rows_split"], t["hist_copies"], t["hist_peel"]) == (7, 4, 2)
+    assert (t["map_rows_split"], t["map_group"], t["map_unit_chunks"]) == (9, 1, 3)
 
 
 def test_plan_count_limits():
