@@ -232,7 +232,10 @@ mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans,
  * Needs ndim >= 2.  The workspace (device, 256-byte aligned) holds one slab
  * of input and output rows, the slab's histograms and LUTs plus the halo:
  * mclahe_chunked_workspace_size().  Asynchronous on hip_stream like
- * mclahe_run; host buffers must stay valid until the stream is done.
+ * mclahe_run: copies run on two internal copy streams of the library that
+ * are ordered against hip_stream by events, and hip_stream completes only
+ * after the last copy; host buffers must stay valid until then.  Calls on
+ * one device are enqueued one at a time.
  * Errors: NOT_SUPPORTED for ndim < 2, INVALID_VALUE for slab_layers < 1,
  * NULL or aliasing buffers, WORKSPACE for a small or misaligned workspace. */
 mclahe_status mclahe_chunked_workspace_size(mclahe_plan_t plan, int slab_layers, size_t *bytes);

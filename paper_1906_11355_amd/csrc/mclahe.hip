@@ -460,7 +460,7 @@ struct ChunkGeom {
     uint32_t range_parts = 0;
     int64_t row_elems = 1, layer_kernels = 1, cols_per_layer = 1, mcols_per_layer = 1;
     int64_t max_rows = 0, max_out_rows = 0;
-    uint64_t o_in, o_in2, o_out, o_part, o_rpart, o_hist, o_clipped, o_range, o_scale, o_lut, o_mrange, o_mscale,
+    uint64_t o_in, o_in2, o_out, o_out2, o_part, o_rpart, o_hist, o_clipped, o_range, o_scale, o_lut, o_mrange, o_mscale,
         total;
 };
 
@@ -540,6 +540,8 @@ static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
     o = align256(o + (uint64_t)g.max_rows * g.row_elems * esize(p->in_dt));
     g.o_out = o;
     o = align256(o + (uint64_t)g.max_out_rows * g.row_elems * esize(p->out_dt));
+    g.o_out2 = o;
+    o = align256(o + (uint64_t)g.max_out_rows * g.row_elems * esize(p->out_dt));
     g.o_part = o;
     o = align256(o + (uint64_t)nhu * v.hG * p->nb * 4);
     g.o_rpart = o;
@@ -566,40 +568,99 @@ static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
     return MCLAHE_SUCCESS;
 }
 
+// Copy streams and events of chunked runs, per device, created on first use
+// and kept for the life of the process (default priority).  Host-to-device
+// copies run on `h2d`, device-to-host copies on `d2h`, kernels on the
+// caller's stream; events order the three.  Runs on one device are
+// serialised by `mu` while they are enqueued.
+struct ChunkStreams {
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t in_ready[2], in_free[2], out_ready[2], out_free[2];
+    std::mutex mu;
+};
+static std::mutex g_chunk_mu;
+static std::map<int, ChunkStreams *> g_chunk_streams;
+
+static mclahe_status chunk_streams(ChunkStreams *&cs)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_chunk_mu);
+    auto it = g_chunk_streams.find(dev);
+    if (it != g_chunk_streams.end()) {
+        cs = it->second;
+        return MCLAHE_SUCCESS;
+    }
+    ChunkStreams *c = new ChunkStreams();
+    HIPCHK(hipStreamCreateWithFlags(&c->h2d, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipEventCreateWithFlags(&c->in_ready[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->in_free[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->out_ready[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->out_free[i], hipEventDisableTiming));
+    }
+    g_chunk_streams[dev] = c;
+    cs = c;
+    return MCLAHE_SUCCESS;
+}
+
+// Two input slab buffers and two output buffers alternate: the upload of
+// the next slab (and of the next range block) overlaps the kernels of the
+// current one, and the download of a slab's output overlaps both.
 static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, const char *h_in, char *h_out,
                                  char *ws, hipStream_t st)
 {
     mclahe_status s;
+    ChunkStreams *cs = nullptr;
+    if ((s = chunk_streams(cs))) return s;
+    std::lock_guard<std::mutex> run_lock(cs->mu);
     const size_t es_in = esize(p->in_dt), es_out = esize(p->out_dt);
     const size_t row_in = (size_t)g.row_elems * es_in, row_out = (size_t)g.row_elems * es_out;
     char *inbuf[2] = {ws + g.o_in, ws + g.o_in2};
-    char *inb = inbuf[0], *outb = ws + g.o_out;
+    char *outbuf[2] = {ws + g.o_out, ws + g.o_out2};
+    bool in_used[2] = {false, false}, out_used[2] = {false, false};
     const size_t layer_lut = (size_t)g.layer_kernels * p->nb;   // floats per LUT layer
     float *lutb = (float *)(ws + g.o_lut);
     float *mrange = (float *)(ws + g.o_mrange), *mscale = (float *)(ws + g.o_mscale);
     const bool ahr = p->mode == MC_AHR;
     size_t lds = 0;
+    int nin = 0;   // input buffer uses so far (range blocks, then slabs)
+
+    // upload rows [r0, r1) of the host volume to input buffer X at row
+    // offset `at` (rows before `at` were filled otherwise), on the copy stream
+    auto upload = [&](int X, int64_t at, int64_t r0, int64_t r1) -> mclahe_status {
+        if (in_used[X]) HIPCHK(hipStreamWaitEvent(cs->h2d, cs->in_free[X], 0));
+        HIPCHK(hipMemcpyAsync(inbuf[X] + (size_t)at * row_in, h_in + (size_t)r0 * row_in,
+                              (size_t)(r1 - r0) * row_in, hipMemcpyHostToDevice, cs->h2d));
+        HIPCHK(hipEventRecord(cs->in_ready[X], cs->h2d));
+        HIPCHK(hipStreamWaitEvent(st, cs->in_ready[X], 0));
+        return MCLAHE_SUCCESS;
+    };
 
     // 1. global range: one streamed min/max pass (partials stay on the device)
     uint32_t rp = 0;
-    for (size_t b = 0; b < g.rr0.size(); ++b) {
-        const int64_t rows = g.rr1[b] - g.rr0[b];
-        HIPCHK(hipMemcpyAsync(inb, h_in + (size_t)g.rr0[b] * row_in, (size_t)rows * row_in,
-                              hipMemcpyHostToDevice, st));
+    for (size_t b = 0; b < g.rr0.size(); ++b, ++nin) {
+        const int X = nin & 1;
+        if ((s = upload(X, 0, g.rr0[b], g.rr1[b]))) return s;
         McVol v = p->v;
-        v.in = inb;
-        v.nvox = rows * g.row_elems;
+        v.in = inbuf[X];
+        v.nvox = (g.rr1[b] - g.rr0[b]) * g.row_elems;
         v.n_range_wu = g.rparts[b];
         v.rpart = (float *)(ws + g.o_rpart) + 2 * (size_t)rp;
         if (v.vec > 1 && (v.nvox % v.vec)) v.vec = 1;
         const KPair k = phase_kernels(p, v, 0, lds);
         if ((s = launch(k.plain, v.n_range_wu, k.threads, lds, st, v))) return s;
+        HIPCHK(hipEventRecord(cs->in_free[X], st));
+        in_used[X] = true;
         rp += g.rparts[b];
     }
 
     // 2. slabs: histograms, clip/CDF/LUT, interpolation
-    for (size_t j = 0; j < g.kA.size(); ++j) {
+    int prevX = -1;
+    for (size_t j = 0; j < g.kA.size(); ++j, ++nin) {
         const int kA = g.kA[j], kB = g.kB[j], nl = kB - kA;
+        const int X = nin & 1, Y = (int)(j & 1);
         if (j > 0) {
             // the previous slab's last LUT layer becomes the halo layer 0
             const int last = g.kB[j - 1] - g.kA[j - 1];
@@ -613,17 +674,17 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             }
         }
         // slab buffer: halo rows [base, hr0) from the previous slab's buffer
-        // (device to device), then the new rows [hr0, hr1) from the host
-        char *cur = inbuf[j & 1];
+        // (device to device, on the copy stream after that buffer's upload),
+        // then the new rows [hr0, hr1) from the host
+        char *cur = inbuf[X];
         const int64_t base = g.base[j];
         if (g.hr0[j] > base) {
-            const char *prev = inbuf[(j - 1) & 1];
-            HIPCHK(hipMemcpyAsync(cur, prev + (size_t)(base - g.base[j - 1]) * row_in,
-                                  (size_t)(g.hr0[j] - base) * row_in, hipMemcpyDeviceToDevice, st));
+            if (in_used[X]) HIPCHK(hipStreamWaitEvent(cs->h2d, cs->in_free[X], 0));
+            in_used[X] = false;   // waited above
+            HIPCHK(hipMemcpyAsync(cur, inbuf[prevX] + (size_t)(base - g.base[j - 1]) * row_in,
+                                  (size_t)(g.hr0[j] - base) * row_in, hipMemcpyDeviceToDevice, cs->h2d));
         }
-        const int64_t hrows = g.hr1[j] - g.hr0[j];
-        HIPCHK(hipMemcpyAsync(cur + (size_t)(g.hr0[j] - base) * row_in, h_in + (size_t)g.hr0[j] * row_in,
-                              (size_t)hrows * row_in, hipMemcpyHostToDevice, st));
+        if ((s = upload(X, g.hr0[j] - base, g.hr0[j], g.hr1[j]))) return s;
         McVol v = p->v;
         v.wk0 = kA;
         v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
@@ -650,26 +711,40 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             if ((s = launch(k.plain, mc_phase_units(v, ph), k.threads, lds, st, v))) return s;
         }
         const int cA = g.cA[j], cB = g.cB[j];
-        if (cB <= cA) continue;
-        const int64_t mrows = g.mr1[j] - g.mr0[j];
-        McVol m = v;
-        m.wc0 = cA;
-        m.n_map_wu = (uint32_t)((int64_t)(cB - cA) * g.mcols_per_layer * v.mS * v.mU);
-        m.in = cur - (size_t)base * row_in;
-        m.out = outb - (size_t)g.mr0[j] * row_out;
-        // LUT layer 0 of the buffer is global kernel layer kA - 1
-        m.lut = lutb - (int64_t)(kA - 1) * (int64_t)layer_lut;
-        if (ahr) {
-            m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
-            m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
+        if (cB > cA) {
+            const int64_t mrows = g.mr1[j] - g.mr0[j];
+            McVol m = v;
+            m.wc0 = cA;
+            m.n_map_wu = (uint32_t)((int64_t)(cB - cA) * g.mcols_per_layer * v.mS * v.mU);
+            m.in = cur - (size_t)base * row_in;
+            m.out = outbuf[Y] - (size_t)g.mr0[j] * row_out;
+            // LUT layer 0 of the buffer is global kernel layer kA - 1
+            m.lut = lutb - (int64_t)(kA - 1) * (int64_t)layer_lut;
+            if (ahr) {
+                m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
+                m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
+            }
+            m.vec = p->v.vec;
+            if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.vec = 1;
+            if (out_used[Y]) HIPCHK(hipStreamWaitEvent(st, cs->out_free[Y], 0));
+            const KPair k = phase_kernels(p, m, 3, lds);
+            if ((s = launch(k.plain, m.n_map_wu, k.threads, lds, st, m))) return s;
+            HIPCHK(hipEventRecord(cs->out_ready[Y], st));
+            HIPCHK(hipStreamWaitEvent(cs->d2h, cs->out_ready[Y], 0));
+            HIPCHK(hipMemcpyAsync(h_out + (size_t)g.mr0[j] * row_out, outbuf[Y], (size_t)mrows * row_out,
+                                  hipMemcpyDeviceToHost, cs->d2h));
+            HIPCHK(hipEventRecord(cs->out_free[Y], cs->d2h));
+            out_used[Y] = true;
         }
-        m.vec = p->v.vec;
-        if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.vec = 1;
-        const KPair k = phase_kernels(p, m, 3, lds);
-        if ((s = launch(k.plain, m.n_map_wu, k.threads, lds, st, m))) return s;
-        HIPCHK(hipMemcpyAsync(h_out + (size_t)g.mr0[j] * row_out, outb, (size_t)mrows * row_out,
-                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(cs->in_free[X], st));
+        in_used[X] = true;
+        prevX = X;
     }
+    // the caller's stream completes only after the last download
+    for (int Y = 0; Y < 2; ++Y)
+        if (out_used[Y]) HIPCHK(hipStreamWaitEvent(st, cs->out_free[Y], 0));
+    for (int X = 0; X < 2; ++X)
+        if (in_used[X]) HIPCHK(hipStreamWaitEvent(cs->h2d, cs->in_free[X], 0));
     return MCLAHE_SUCCESS;
 }
 
