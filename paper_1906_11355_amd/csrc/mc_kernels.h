@@ -37,10 +37,10 @@ __device__ __forceinline__ int bin_of(float v, float lo, float scale, float nbf,
 {
     (void)nbf;
     const float t = (v - lo) * scale;
-    // t >= n-1 truncates to n-1 either way; fminf maps NaN to n-1, which the
-    // t > 0 test then sends to bin 0 as the reading requires
-    const int r = (int)fminf(t, (float)nbm1);
-    return (t > 0.0f) ? r : 0;
+    // v_cvt_u32_f32 truncates toward zero and saturates: t <= 0 and NaN give
+    // 0, t >= 2^32 gives 2^32 - 1; the unsigned min then caps at n - 1.  So
+    // !(t > 0) -> 0, t >= n -> n - 1, else (int)t, in two instructions.
+    return (int)min(__float2uint_rz(t), (unsigned)nbm1);
 }
 
 __device__ __forceinline__ float range_scale(int nb, float lo, float hi)
