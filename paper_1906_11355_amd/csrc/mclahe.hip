@@ -298,10 +298,20 @@ static mclahe_status derive(mclahe_plan_s *p)
         if (i <= D - 3) omax_m *= p->ax[i].b;
     }
     const int64_t crmin_m = fast ? std::max<int64_t>(1, (omax_m + MC_OMAX - 5) / (MC_OMAX - 4)) : 1;
-    // default row split: enough chunks for ~2048 units; under a global range
-    // (where a unit runs several chunks on one LUT staging) also chunks of at
-    // most ~800 rows, the fastest measured at the 4D workload
-    int64_t mcr = (2048 + v.mCols * v.mS - 1) / (v.mCols * v.mS);
+    // default row split: enough chunks for ~2048 units, but no chunk under
+    // ~16K voxels (a unit's LUT staging dominates small ones); under a global
+    // range (where a unit runs several chunks on one LUT staging) also chunks
+    // of at most ~800 rows, the fastest measured at the 4D workload
+    int64_t segw = 0;   // widest last-axis extent of a unit
+    for (int cA = 0; cA < ncl; cA += mG) {
+        int xs, xe, tmp;
+        mc_cell_range(al, cA, xs, tmp);
+        mc_cell_range(al, std::min(cA + mG, ncl) - 1, tmp, xe);
+        segw = std::max<int64_t>(segw, xe - xs);
+    }
+    if (mP > 1) segw = (segw + mP - 1) / mP;
+    int64_t mcr = std::min<int64_t>((2048 + v.mCols * v.mS - 1) / (v.mCols * v.mS),
+                                    std::max<int64_t>(1, rmax_m * segw / 16384));
     if (fast && p->mode == MC_GHR) mcr = std::max<int64_t>(mcr, (rmax_m + 799) / 800);
     if (t.map_rows_split > 0) mcr = t.map_rows_split;
     mcr = std::max<int64_t>(mcr, crmin_m);
