@@ -111,7 +111,7 @@ typedef struct {
  *   hist_rows_split   : row chunks per kernel column in the histogram pass
  *   hist_copies       : LDS histogram replicas (1, 2, 4, 8) against bin collisions
  *   hist_peel         : wavefront aggregation of colliding bins: 1 = off,
- *                       2 = one round, 3 = two rounds (0 = default)
+ *                       2 or 3 = one round (0 = default, off)
  *   map_rows_split    : row chunks per cell column in the interpolation pass
  *   map_group         : interpolation cells per work unit along the last axis
  *   map_unit_chunks   : row chunks an interpolation unit runs on one staging of

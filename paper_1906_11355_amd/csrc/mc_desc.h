@@ -105,6 +105,10 @@ MC_HD int32_t mc_lut_stride(int32_t nlk, int32_t NO)
 // plus one word so that the stride is odd and slots spread over the banks.
 MC_HD int32_t mc_hist_slot_stride(int32_t nb, int32_t R) { return nb * R + 1; }
 
+// Elements per chunk of a row: 16 bytes (4 floats, 8 uint16), but 8 uint8,
+// which keeps the per-element registers of a thread bounded.
+MC_HD constexpr int mc_vec_elems(int esize) { return esize == 1 ? 8 : 16 / esize; }
+
 // Work-group size of the LDS-staged map kernels.
 MC_HD constexpr int mc_map_threads(bool ahr) { return ahr ? MC_T : MC_MAP_T; }
 
@@ -118,7 +122,9 @@ struct McVol {
     McAxis ax[MC_MAXD];
     int64_t stride[MC_MAXD];  // element strides (C-contiguous)
     int64_t nvox, nker;
-    int32_t vec;              // elements per vector chunk (1 or 16/sizeof(in))
+    int32_t vec;              // elements per chunk (1 or 16/sizeof(in))
+    int32_t sload;            // 1: chunks are loaded element by element (rows
+                              //    not 16-byte aligned), 0: one 16-byte load
     int32_t path;             // 0 = LDS-staged fast map, 1 = generic map
     // ---- histogram / adaptive-range work units ------------------------------
     int32_t hG, hP, hS, hCr;  // kernels per segment, parts per kernel,

@@ -63,21 +63,32 @@ __device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)
     if constexpr (V == 1) {
         f[0] = (float)p[0];
     } else {
-        static_assert(V * sizeof(Tin) == 16, "wide chunk is 16 bytes");
-        const uint4 q = *reinterpret_cast<const uint4 *>(p);
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        constexpr int NW = V * (int)sizeof(Tin) / 4;   // 32-bit words: 4 or 2
+        static_assert(NW == 4 || NW == 2, "a chunk is 16 or 8 bytes");
+        uint32_t w[NW];
+        if constexpr (NW == 4) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(p);
+            w[0] = q.x;
+            w[1] = q.y;
+            w[2] = q.z;
+            w[3] = q.w;
+        } else {
+            const uint2 q = *reinterpret_cast<const uint2 *>(p);
+            w[0] = q.x;
+            w[1] = q.y;
+        }
         if constexpr (sizeof(Tin) == 4) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
+            for (int i = 0; i < NW; ++i) f[i] = __uint_as_float(w[i]);
         } else if constexpr (sizeof(Tin) == 2) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NW; ++i) {
                 f[2 * i] = (float)(w[i] & 0xffffu);
                 f[2 * i + 1] = (float)(w[i] >> 16);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NW; ++i) {
                 f[4 * i] = (float)(w[i] & 0xffu);
                 f[4 * i + 1] = (float)((w[i] >> 8) & 0xffu);
                 f[4 * i + 2] = (float)((w[i] >> 16) & 0xffu);
@@ -85,6 +96,17 @@ __device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)
             }
         }
     }
+}
+
+// A chunk of V elements of a row whose start is not vector aligned (rows
+// of a length that is no multiple of V, or a misaligned buffer): element
+// loads, only for the nval elements that lie in the row (the others read 0
+// and are never used).
+template <typename Tin, int V>
+__device__ __forceinline__ void load_chunk_sl(const Tin *__restrict__ p, float (&f)[V], int nval)
+{
+#pragma unroll
+    for (int e = 0; e < V; ++e) f[e] = e < nval ? (float)p[e] : 0.0f;
 }
 
 __device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
@@ -351,8 +373,9 @@ __device__ void range_ghr_unit_v(const McVol &d, uint32_t u, float *red)
 template <typename Tin>
 __device__ void range_ghr_unit(const McVol &d, uint32_t u, char *smem)
 {
-    constexpr int VM = 16 / sizeof(Tin);
-    if (d.vec == VM) range_ghr_unit_v<Tin, VM>(d, u, (float *)smem);
+    constexpr int VM = mc_vec_elems((int)sizeof(Tin));
+    // flat over the volume: vector loads need only an aligned base
+    if (d.vec == VM && ((uintptr_t)d.in & 15) == 0) range_ghr_unit_v<Tin, VM>(d, u, (float *)smem);
     else range_ghr_unit_v<Tin, 1>(d, u, (float *)smem);
 }
 
@@ -594,6 +617,8 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int64_t so = rpi / rs.in_len;
         const int sr = (int)(rpi - so * rs.in_len);
         const int64_t xoff = (int64_t)(c_lo + tch) * V;
+        const bool sl = V > 1 && d.sload;                 // element loads
+        const int nval = (int)mc_min((int64_t)V, (int64_t)d.ax[D - 1].s - xoff);
         // U rows per step.  Software pipelined: the loads of the next U rows
         // are issued before the current U rows are binned, so every wave
         // keeps up to 2U wide loads in flight while it works.
@@ -616,7 +641,10 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (okk[u]) load_chunk<Tin, V>(in + offs[u], fl[u]);
+                if (okk[u]) {
+                    if (sl) load_chunk_sl<Tin, V>(in + offs[u], fl[u], nval);
+                    else load_chunk<Tin, V>(in + offs[u], fl[u]);
+                }
         };
         auto process = [&](int64_t rw, const uint32_t (&wr)[U], const bool (&okk)[U], const float (&fl)[U][V]) {
 #pragma unroll
@@ -726,7 +754,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
 template <typename Tin, bool AHR, bool RANGE_ONLY, int PEEL>
 __device__ void hist_unit_dispatch(const McVol &d, uint32_t wu, char *smem)
 {
-    constexpr int VM = 16 / sizeof(Tin);
+    constexpr int VM = mc_vec_elems((int)sizeof(Tin));
     if (d.vec == VM) hist_unit_v<Tin, VM, AHR, RANGE_ONLY, PEEL>(d, wu, smem);
     else hist_unit_v<Tin, 1, AHR, RANGE_ONLY, PEEL>(d, wu, smem);
 }
@@ -969,7 +997,9 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int nbm1 = nb - 1;
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
-    const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
+    const bool sl = V > 1 && d.sload;                     // element loads
+    const int nval = (int)mc_min((int64_t)V, (int64_t)al.s - xoff);
+    const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv && !sl;
     // the unit's row chunks, one after another on the same staged LUTs; the
     // outer-row table is rebuilt for each chunk
     // (per-kernel range: one chunk per unit, which keeps its 2^D ranges in
@@ -1038,7 +1068,10 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             float fu[U][V];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
+                if (ok[u]) {
+                    if (sl) load_chunk_sl<Tin, V>(in + offs[u], fu[u], nval);
+                    else load_chunk<Tin, V>(in + offs[u], fu[u]);
+                }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!ok[u]) break;
@@ -1126,7 +1159,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
 template <typename Tin, int D, bool AHR>
 __device__ void map_unit(const McVol &d, uint32_t wu, char *smem)
 {
-    constexpr int VM = 16 / sizeof(Tin);
+    constexpr int VM = mc_vec_elems((int)sizeof(Tin));
     if (d.vec == VM) map_unit_v<Tin, D, AHR, VM>(d, wu, smem);
     else map_unit_v<Tin, D, AHR, 1>(d, wu, smem);
 }

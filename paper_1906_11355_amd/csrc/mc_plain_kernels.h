@@ -84,10 +84,8 @@ template <typename Tin>
 static KPair pick_hist_t(bool ahr, bool ro, int peel)
 {
     if (ro) return hist_pair<Tin, true, true, 0>();
-    if (ahr) return peel == 0 ? hist_pair<Tin, true, false, 0>()
-                  : peel == 1 ? hist_pair<Tin, true, false, 1>() : hist_pair<Tin, true, false, 2>();
-    return peel == 0 ? hist_pair<Tin, false, false, 0>()
-         : peel == 1 ? hist_pair<Tin, false, false, 1>() : hist_pair<Tin, false, false, 2>();
+    if (ahr) return peel == 0 ? hist_pair<Tin, true, false, 0>() : hist_pair<Tin, true, false, 1>();
+    return peel == 0 ? hist_pair<Tin, false, false, 0>() : hist_pair<Tin, false, false, 1>();
 }
 
 template <typename Tin, int D, bool AHR>

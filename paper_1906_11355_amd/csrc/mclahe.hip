@@ -128,9 +128,12 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.nvox = p->nvox;
     v.nker = p->nker;
     const McAxis &al = p->ax[D - 1];
-    const int vmax = 16 / (int)esize(p->in_dt);
-    const int V = (al.s % vmax == 0) ? vmax : 1;
+    const int vmax = mc_vec_elems((int)esize(p->in_dt));
+    // chunks of 16 bytes: one vector load when every row starts 16-byte
+    // aligned, element loads otherwise (rows long enough to fill chunks)
+    const int V = (al.s % vmax == 0 || al.s >= 4 * vmax) ? vmax : 1;
     v.vec = V;
+    v.sload = (V > 1 && al.s % vmax != 0) ? 1 : 0;
     const int maxchunks = MC_T - 1;
     const mclahe_tuning &t = p->tune;
 
@@ -184,7 +187,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.hS = P == 1 ? (al.n + G - 1) / G : al.n * P;
     v.hR = R;
     // hist_peel: 0 = default (no aggregation), k >= 1 = k - 1 rounds
-    v.hPeel = t.hist_peel > 0 ? std::min(t.hist_peel - 1, 2) : 0;
+    v.hPeel = t.hist_peel > 1 ? 1 : 0;   // one aggregation round (a second only spilled)
     v.hCols = 1;
     int64_t omax_h = 1, rmax_h = 1;
     for (int i = 0; i < D - 1; ++i) {
@@ -376,7 +379,7 @@ static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, ch
     v.range = (float *)(ws + p->o_range);
     v.scale = (float *)(ws + p->o_scale);
     const size_t es_in = esize(p->in_dt);
-    if (v.vec > 1 && (((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0)) v.vec = 1;
+    if (v.vec > 1 && (((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0)) v.sload = 1;
     (void)es_in;
 }
 
@@ -658,7 +661,7 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
         v.nvox = (g.rr1[b] - g.rr0[b]) * g.row_elems;
         v.n_range_wu = g.rparts[b];
         v.rpart = (float *)(ws + g.o_rpart) + 2 * (size_t)rp;
-        if (v.vec > 1 && (v.nvox % v.vec)) v.vec = 1;
+
         const KPair k = phase_kernels(p, v, 0, lds);
         if ((s = launch(k.plain, v.n_range_wu, k.threads, lds, st, v))) return s;
         HIPCHK(hipEventRecord(cs->in_free[X], st));
@@ -714,7 +717,7 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             v.range = (float *)(ws + g.o_range);
             v.scale = (float *)(ws + g.o_scale);
         }
-        if (v.vec > 1 && ((uintptr_t)v.in % 16)) v.vec = 1;
+        if (v.vec > 1 && ((uintptr_t)v.in % 16)) v.sload = 1;
         for (int ph = 0; ph < 3; ++ph) {
             const KPair k = phase_kernels(p, v, ph, lds);
             if (ph == 0 && !ahr) continue;            // GHR range done above
@@ -734,8 +737,8 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
                 m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
                 m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
             }
-            m.vec = p->v.vec;
-            if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.vec = 1;
+            m.sload = p->v.sload;
+            if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.sload = 1;
             if (out_used[Y]) HIPCHK(hipStreamWaitEvent(st, cs->out_free[Y], 0));
             const KPair k = phase_kernels(p, m, 3, lds);
             if ((s = launch(k.plain, m.n_map_wu, k.threads, lds, st, m))) return s;
@@ -1012,7 +1015,7 @@ static std::vector<mclahe_tuning> tune_candidates(const mclahe_plan_s *p)
     const McVol &v = p->v;
     const int hcr = v.hCr, mcr = v.mCr;
     for (int R : {1, 2, 4})
-        for (int peel : {1, 2, 3})
+        for (int peel : {1, 2})
             for (int f : {1, 2, 4}) {
                 mclahe_tuning t = {};
                 t.hist_copies = R;

@@ -86,6 +86,19 @@ def test_large_bins_generic_map():
     _case(x, (5, 4, 3, 4), 1024, 0.02, "kernel")
 
 
+def test_max_bins_and_vector_widths():
+    """8192 bins (the limit), and each input dtype on rows a whole number of
+    16-byte vectors long (u8: 16 per load, u16: 8, f32: 4) in both modes."""
+    rng = np.random.default_rng(12)
+    x = rng.gamma(2.0, 300.0, size=(24, 20, 16)).astype(np.float32)
+    _case(x, (8, 7, 5), 8192, 0.02, "global")
+    _case(x, (8, 7, 5), 8192, 0.02, "kernel")
+    for dt, hi, last in ((np.uint8, 255, 96), (np.uint16, 60000, 88), (np.float32, 1000, 36)):
+        y = rng.integers(0, hi, size=(30, 17, last)).astype(dt)
+        _case(y, (9, 5, 16), 256, 0.02, "global")
+        _case(y, (9, 5, 16), 128, 0.02, "kernel", out_dtype=np.uint16)
+
+
 # --------------------------------------------------- decomposition regimes
 def test_long_last_axis_split_kernels():
     """Kernels longer than one work-group row: split histogram and cell parts."""
