@@ -91,7 +91,10 @@ typedef struct mclahe_plan_s *mclahe_plan_t;
  *   lut     : f32 [N_k][n]   normalised CDF maps
  *   range   : f32 [N_k][2] (AHR) or [2] (GHR), lo then hi
  *   scale   : f32 [N_k] (AHR) or [1] (GHR), (float)n / (hi - lo)
- *   total   : bytes needed                                                  */
+ *   total   : bytes needed
+ * These arrays come first; per-work-unit partials follow them.  The offsets
+ * are the same when the plan runs in a batch (whose default work units are
+ * coarser, so its per-volume workspace is at most `total`).                */
 typedef struct {
     uint64_t hist, clipped, lut, range, scale, total;
 } mclahe_layout;

@@ -122,9 +122,7 @@ struct McVol {
     McAxis ax[MC_MAXD];
     int64_t stride[MC_MAXD];  // element strides (C-contiguous)
     int64_t nvox, nker;
-    int32_t vec;              // elements per chunk (1 or 16/sizeof(in))
-    int32_t sload;            // 1: chunks are loaded element by element (rows
-                              //    not 16-byte aligned), 0: one 16-byte load
+    int32_t vec;              // elements per vector chunk (1 or mc_vec_elems)
     int32_t path;             // 0 = LDS-staged fast map, 1 = generic map
     // ---- histogram / adaptive-range work units ------------------------------
     int32_t hG, hP, hS, hCr;  // kernels per segment, parts per kernel,

@@ -98,17 +98,6 @@ __device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)
     }
 }
 
-// A chunk of V elements of a row whose start is not vector aligned (rows
-// of a length that is no multiple of V, or a misaligned buffer): element
-// loads, only for the nval elements that lie in the row (the others read 0
-// and are never used).
-template <typename Tin, int V>
-__device__ __forceinline__ void load_chunk_sl(const Tin *__restrict__ p, float (&f)[V], int nval)
-{
-#pragma unroll
-    for (int e = 0; e < V; ++e) f[e] = e < nval ? (float)p[e] : 0.0f;
-}
-
 __device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
 {
     if (dt == MC_U8) return (float)((const uint8_t *)in)[i];
@@ -375,7 +364,7 @@ __device__ void range_ghr_unit(const McVol &d, uint32_t u, char *smem)
 {
     constexpr int VM = mc_vec_elems((int)sizeof(Tin));
     // flat over the volume: vector loads need only an aligned base
-    if (d.vec == VM && ((uintptr_t)d.in & 15) == 0) range_ghr_unit_v<Tin, VM>(d, u, (float *)smem);
+    if (((uintptr_t)d.in & 15) == 0) range_ghr_unit_v<Tin, VM>(d, u, (float *)smem);
     else range_ghr_unit_v<Tin, 1>(d, u, (float *)smem);
 }
 
@@ -617,8 +606,6 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int64_t so = rpi / rs.in_len;
         const int sr = (int)(rpi - so * rs.in_len);
         const int64_t xoff = (int64_t)(c_lo + tch) * V;
-        const bool sl = V > 1 && d.sload;                 // element loads
-        const int nval = (int)mc_min((int64_t)V, (int64_t)d.ax[D - 1].s - xoff);
         // U rows per step.  Software pipelined: the loads of the next U rows
         // are issued before the current U rows are binned, so every wave
         // keeps up to 2U wide loads in flight while it works.
@@ -641,10 +628,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (okk[u]) {
-                    if (sl) load_chunk_sl<Tin, V>(in + offs[u], fl[u], nval);
-                    else load_chunk<Tin, V>(in + offs[u], fl[u]);
-                }
+                if (okk[u]) load_chunk<Tin, V>(in + offs[u], fl[u]);
         };
         auto process = [&](int64_t rw, const uint32_t (&wr)[U], const bool (&okk)[U], const float (&fl)[U][V]) {
 #pragma unroll
@@ -997,9 +981,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int nbm1 = nb - 1;
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
-    const bool sl = V > 1 && d.sload;                     // element loads
-    const int nval = (int)mc_min((int64_t)V, (int64_t)al.s - xoff);
-    const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv && !sl;
+    const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
     // the unit's row chunks, one after another on the same staged LUTs; the
     // outer-row table is rebuilt for each chunk
     // (per-kernel range: one chunk per unit, which keeps its 2^D ranges in
@@ -1068,10 +1050,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             float fu[U][V];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u]) {
-                    if (sl) load_chunk_sl<Tin, V>(in + offs[u], fu[u], nval);
-                    else load_chunk<Tin, V>(in + offs[u], fu[u]);
-                }
+                if (ok[u]) load_chunk<Tin, V>(in + offs[u], fu[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!ok[u]) break;

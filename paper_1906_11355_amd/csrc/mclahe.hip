@@ -65,7 +65,20 @@ struct mclahe_plan_s {
     // workspace layout
     uint64_t o_part, o_rpart, o_hist, o_clipped, o_lut, o_range, o_scale, total;
     size_t lds_range, lds_hist, lds_clip, lds_map;
+    // the same for batched launches, whose default work units are coarser
+    // (many volumes fill the chip together)
+    struct {
+        McVol v;
+        uint64_t o_part, o_rpart, o_hist, o_clipped, o_lut, o_range, o_scale, total;
+        size_t lds_range, lds_hist, lds_clip, lds_map;
+    } bd;
 };
+
+// Default minimum voxels per histogram / interpolation work unit: a unit's
+// fixed cost (staging and flushing its LDS arrays) dominates smaller ones.
+// Batched launches fill the chip with the units of many volumes, so they take
+// coarser units.
+static const int64_t kUnitVoxPlain = 16384, kUnitVoxBatch = 65536;
 
 static size_t esize(int dt) { return dt == MC_U8 ? 1 : dt == MC_U16 ? 2 : 4; }
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
@@ -105,8 +118,9 @@ static void seg_extent(const McAxis &a, int kA, int kB, int &xs, int &xe)
 // Chunks of V elements a segment [xs, xe) spans.
 static int seg_chunks(int xs, int xe, int V) { return (xe + V - 1) / V - xs / V; }
 
-// Derive the work decomposition and workspace layout from the tuning.
-static mclahe_status derive(mclahe_plan_s *p)
+// Derive the work decomposition and workspace layout from the tuning, with
+// default work units of at least unit_vox voxels.
+static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox)
 {
     McVol &v = p->v;
     memset(&v, 0, sizeof v);
@@ -129,11 +143,8 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.nker = p->nker;
     const McAxis &al = p->ax[D - 1];
     const int vmax = mc_vec_elems((int)esize(p->in_dt));
-    // chunks of 16 bytes: one vector load when every row starts 16-byte
-    // aligned, element loads otherwise (rows long enough to fill chunks)
-    const int V = (al.s % vmax == 0 || al.s >= 4 * vmax) ? vmax : 1;
+    const int V = (al.s % vmax == 0) ? vmax : 1;
     v.vec = V;
-    v.sload = (V > 1 && al.s % vmax != 0) ? 1 : 0;
     const int maxchunks = MC_T - 1;
     const mclahe_tuning &t = p->tune;
 
@@ -221,7 +232,7 @@ static mclahe_status derive(mclahe_plan_s *p)
         seglen = std::max<int64_t>(seglen, (int64_t)(xe - xs));
     }
     const int64_t cr_units = (2048 + v.hCols * v.hS - 1) / (v.hCols * v.hS);
-    const int64_t cr_work = std::max<int64_t>(1, rmax_h * seglen / 16384);
+    const int64_t cr_work = std::max<int64_t>(1, rmax_h * seglen / unit_vox);
     int64_t cr = t.hist_rows_split > 0 ? t.hist_rows_split : std::min(cr_units, cr_work);
     cr = std::max<int64_t>(cr, crmin_h);
     cr = std::min<int64_t>(cr, std::max<int64_t>(rmax_h, crmin_h));
@@ -314,7 +325,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     }
     if (mP > 1) segw = (segw + mP - 1) / mP;
     int64_t mcr = std::min<int64_t>((2048 + v.mCols * v.mS - 1) / (v.mCols * v.mS),
-                                    std::max<int64_t>(1, rmax_m * segw / 16384));
+                                    std::max<int64_t>(1, rmax_m * segw / unit_vox));
     if (fast && p->mode == MC_GHR) mcr = std::max<int64_t>(mcr, (rmax_m + 799) / 800);
     if (t.map_rows_split > 0) mcr = t.map_rows_split;
     mcr = std::max<int64_t>(mcr, crmin_m);
@@ -339,13 +350,11 @@ static mclahe_status derive(mclahe_plan_s *p)
     v.n_map_wu = (uint32_t)nmu;
 
     // ---- workspace layout -------------------------------------------------
+    // The per-kernel arrays come first: their offsets depend only on the
+    // problem, so they are the same in the plain and the batched
+    // decomposition; the per-unit partials, whose sizes depend on the work
+    // units, come last.
     uint64_t o = 0;
-    p->o_part = o;
-    o = align256(o + (uint64_t)v.n_hist_wu * v.hG * v.nb * 4);
-    p->o_rpart = o;
-    const uint64_t nrp = p->mode == MC_GHR ? (uint64_t)std::max<uint32_t>(v.n_range_wu, 1) * 2
-                                           : (uint64_t)v.n_hist_wu * v.hG * 2;
-    o = align256(o + nrp * 4);
     p->o_hist = o;
     o = align256(o + (uint64_t)p->nker * p->nb * 4);
     p->o_clipped = o;
@@ -356,6 +365,12 @@ static mclahe_status derive(mclahe_plan_s *p)
     o = align256(o + (p->mode == MC_AHR ? (uint64_t)p->nker * 2 : 2) * 4);
     p->o_scale = o;
     o = align256(o + (p->mode == MC_AHR ? (uint64_t)p->nker : 1) * 4);
+    p->o_part = o;
+    o = align256(o + (uint64_t)v.n_hist_wu * v.hG * v.nb * 4);
+    p->o_rpart = o;
+    const uint64_t nrp = p->mode == MC_GHR ? (uint64_t)std::max<uint32_t>(v.n_range_wu, 1) * 2
+                                           : (uint64_t)v.n_hist_wu * v.hG * 2;
+    o = align256(o + nrp * 4);
     p->total = o;
 
     p->lds_range = 2 * MC_T * 4;
@@ -363,6 +378,47 @@ static mclahe_status derive(mclahe_plan_s *p)
     p->lds_clip = MC_T * 8;
     p->lds_map = fast ? otab + map_lut_bytes(p, v.mG) : 0;
     return MCLAHE_SUCCESS;
+}
+
+// Both decompositions: the batched one (kept in p->bd), then the plain one.
+static mclahe_status derive(mclahe_plan_s *p)
+{
+    mclahe_status s = derive_core(p, kUnitVoxBatch);
+    if (s) return s;
+    p->bd.v = p->v;
+    p->bd.o_part = p->o_part;
+    p->bd.o_rpart = p->o_rpart;
+    p->bd.o_hist = p->o_hist;
+    p->bd.o_clipped = p->o_clipped;
+    p->bd.o_lut = p->o_lut;
+    p->bd.o_range = p->o_range;
+    p->bd.o_scale = p->o_scale;
+    p->bd.total = p->total;
+    p->bd.lds_range = p->lds_range;
+    p->bd.lds_hist = p->lds_hist;
+    p->bd.lds_clip = p->lds_clip;
+    p->bd.lds_map = p->lds_map;
+    return derive_core(p, kUnitVoxPlain);
+}
+
+// A copy of the plan that carries the batched decomposition, for the
+// batched entry points (same problem, same bits, coarser default units).
+static void batch_view(const mclahe_plan_s *p, mclahe_plan_s &q)
+{
+    q = *p;
+    q.v = p->bd.v;
+    q.o_part = p->bd.o_part;
+    q.o_rpart = p->bd.o_rpart;
+    q.o_hist = p->bd.o_hist;
+    q.o_clipped = p->bd.o_clipped;
+    q.o_lut = p->bd.o_lut;
+    q.o_range = p->bd.o_range;
+    q.o_scale = p->bd.o_scale;
+    q.total = p->bd.total;
+    q.lds_range = p->bd.lds_range;
+    q.lds_hist = p->bd.lds_hist;
+    q.lds_clip = p->bd.lds_clip;
+    q.lds_map = p->bd.lds_map;
 }
 
 // Pointers of a run's descriptor.
@@ -379,7 +435,7 @@ static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, ch
     v.range = (float *)(ws + p->o_range);
     v.scale = (float *)(ws + p->o_scale);
     const size_t es_in = esize(p->in_dt);
-    if (v.vec > 1 && (((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0)) v.sload = 1;
+    if (v.vec > 1 && (((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0)) v.vec = 1;
     (void)es_in;
 }
 
@@ -717,7 +773,7 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             v.range = (float *)(ws + g.o_range);
             v.scale = (float *)(ws + g.o_scale);
         }
-        if (v.vec > 1 && ((uintptr_t)v.in % 16)) v.sload = 1;
+        if (v.vec > 1 && ((uintptr_t)v.in % 16)) v.vec = 1;
         for (int ph = 0; ph < 3; ++ph) {
             const KPair k = phase_kernels(p, v, ph, lds);
             if (ph == 0 && !ahr) continue;            // GHR range done above
@@ -737,8 +793,8 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
                 m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
                 m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
             }
-            m.sload = p->v.sload;
-            if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.sload = 1;
+            m.vec = p->v.vec;
+            if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.vec = 1;
             if (out_used[Y]) HIPCHK(hipStreamWaitEvent(st, cs->out_free[Y], 0));
             const KPair k = phase_kernels(p, m, 3, lds);
             if ((s = launch(k.plain, m.n_map_wu, k.threads, lds, st, m))) return s;
@@ -780,6 +836,7 @@ struct BatchLaunch {
 };
 
 struct BatchLayout {
+    std::vector<mclahe_plan_s> view;   // the plans with their batched decomposition
     uint64_t o_table, o_recs, o_idx, o_vols, o_first, total;
     std::vector<uint64_t> vol_off;
     std::vector<BatchLaunch> launches;
@@ -791,12 +848,14 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout
     if (n < 1 || !plans) return fail(MCLAHE_ERROR_INVALID_VALUE, "batched call needs n >= 1 plans");
     for (int i = 0; i < n; ++i)
         if (!plans[i]) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan %d is NULL", i);
+    L.view.resize(n);
+    for (int i = 0; i < n; ++i) batch_view(plans[i], L.view[i]);
     // group the volumes of each pass by kernel class
     L.launches.clear();
     for (int ph = 0; ph < MC_PHASES; ++ph) {
         const size_t first = L.launches.size();
         for (int i = 0; i < n; ++i) {
-            const mclahe_plan_s *p = plans[i];
+            const mclahe_plan_s *p = &L.view[i];
             const uint32_t units = mc_phase_units(p->v, ph);
             if (!units) continue;
             size_t lds = 0;
@@ -828,7 +887,7 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout
     L.vol_off.resize(n);
     for (int i = 0; i < n; ++i) {
         L.vol_off[i] = o;
-        o = align256(o + plans[i]->total);
+        o = align256(o + L.view[i].total);
     }
     L.total = o;
     return MCLAHE_SUCCESS;
@@ -844,7 +903,7 @@ static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins
     McLaunchRec *recs = (McLaunchRec *)(img.data() + L.o_recs);
     uint32_t *idx = (uint32_t *)(img.data() + L.o_idx);
     McVol *vols = (McVol *)(img.data() + L.o_vols);
-    for (int i = 0; i < n; ++i) bind(plans[i], vols[i], ins[i], outs[i], vol_ws[i]);
+    for (int i = 0; i < n; ++i) bind(&L.view[i], vols[i], ins[i], outs[i], vol_ws[i]);
     h->nvol = (uint32_t)n;
     h->nlaunch = (uint32_t)L.launches.size();
     uint32_t k = 0;
@@ -1491,7 +1550,8 @@ mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans, const 
     if (!d_in || !d_out || !d_ws || !ws_bytes)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output/workspace arrays are NULL");
     for (int i = 0; i < n; ++i) {
-        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws[i], ws_bytes[i], plans[i]->total);
+        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws[i], ws_bytes[i],
+                           std::max<uint64_t>(plans[i]->total, L.view[i].total));
         if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
     }
     const size_t tb = L.o_first - L.o_table;
