@@ -74,6 +74,8 @@ def parse():
                     help="leave out the mixed batch (batched launches vs per-volume launches)")
     ap.add_argument("--skip-serve", action="store_true", help="leave out the serving sweep")
     ap.add_argument("--skip-chunked", action="store_true", help="leave out the out-of-core run")
+    ap.add_argument("--skip-metrics", action="store_true",
+                    help="leave out the contrast-metric timing and the 3D-per-frame vs 4D table")
     ap.add_argument("--rates", default="10,30,100,300,1000,2000", help="serving arrival rates, req/s")
     ap.add_argument("--skip-configs", action="store_true",
                     help="leave out the 2D/3D configurations and the 4D per-kernel-range run")
@@ -182,6 +184,9 @@ def main():
     if not args.skip_configs:
         res["configs"] = bench_configs(torch, np, _lib, synth, x, dev)
         log(f"configs: {res['configs']}")
+    if not args.skip_metrics:
+        res["metrics"] = bench_metrics(torch, np, _lib, x, g_out, dev)
+        log(f"metrics: {res['metrics']}")
     if not args.skip_chunked:
         res["chunked"] = bench_chunked(torch, np, _lib, x, dev, g_out)
         log(f"chunked: {res['chunked']}")
@@ -283,6 +288,63 @@ def bench_chunked(torch, np, _lib, x, dev, ref_out, steps=3):
             "device_bytes": wsb, "in_core_device_bytes": in_core,
             "bit_identical_to_in_hbm": same,
             "note": "input and output in pinned host memory; includes all PCIe copies"}
+
+
+def bench_metrics(torch, np, _lib, x, g_out, dev, steps=10):
+    """Contrast metrics on the GPU: timing of mclahe_metrics on the headline
+    volume against its result, and the paper's comparison of 4D CLAHE with 3D
+    CLAHE applied to each time frame separately (last axis = time), under a
+    global and an adaptive range, on the synthetic volume."""
+    from paper_1906_11355_amd import api
+    peak = float(2 ** 23)             # the peak both of the paper's tables imply
+    xt = torch.from_numpy(x).to(dev)
+    yt = torch.from_numpy(g_out).to(dev)
+    V, nb = x.size, 256
+    ws = torch.empty(_lib.metrics_workspace_size(V, nb), dtype=torch.uint8, device=dev)
+    res = torch.empty(128, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    call = (xt.data_ptr(), _lib.F32, yt.data_ptr(), _lib.F32, V, nb, peak, res.data_ptr(), None,
+            ws.data_ptr(), ws.numel(), st)
+    for _ in range(3):
+        _lib.metrics_ptr(*call)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        _lib.metrics_ptr(*call)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    one_read = V * (4 + 4)            # each volume read once: what the metrics need
+    two_pass = 2 * one_read           # the two passes (range, then sums and histograms)
+    out = {"ms": round(ms, 4), "Gvoxel_s": round(V / ms / 1e6, 1),
+           "achieved_GBs": round(two_pass / (ms * 1e-3) / 1e9, 1),
+           "frac_of_hbm": round(two_pass / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "alg_bytes": one_read, "bytes_moved_by_design": two_pass, "n_bins": nb}
+
+    def table_row(m):
+        return {"mse": round(m["mse"], 5), "psnr": round(m["psnr"], 2), "std": round(m["std"][1], 4),
+                "ent": round(m["entropy"][1], 3)}
+
+    raw = api.metrics(xt, None, nb)
+    rows = {"raw": {"std": round(raw["std"][0], 4), "ent": round(raw["entropy"][0], 3)}}
+    T = SHAPE[-1]
+    frames = xt.permute(3, 0, 1, 2).contiguous()          # T contiguous 3D frames
+    for mode in ("global", "kernel"):
+        tag = "GHR" if mode == "global" else "AHR"
+        y4 = api.enhance(xt, KSIZE, NBINS, CLIP, mode)
+        plans = [_lib.Plan(SHAPE[:-1], KSIZE[:-1], NBINS, CLIP, mode, in_dtype="float32",
+                           out_dtype="float32") for _ in range(T)]
+        outs = api.enhance_batched([frames[t] for t in range(T)], plans=plans)
+        y3 = torch.stack(outs, dim=-1).contiguous()
+        rows[f"3D CLAHE ({tag})"] = table_row(api.metrics(xt, y3, nb, peak))
+        rows[f"4D CLAHE ({tag})"] = table_row(api.metrics(xt, y4, nb, peak))
+        del y4, y3, outs
+    out["table"] = rows
+    out["table_note"] = ("synthetic photoemission-like volume (not the paper's data); MSE against the "
+                         "min-max normalised raw volume, PSNR with peak 2^23, STD and 256-bin entropy "
+                         "of the result")
+    return out
 
 
 def time_plan(torch, _lib, plan, x, dev, steps):

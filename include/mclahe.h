@@ -269,6 +269,45 @@ mclahe_status mclahe_run_timed(mclahe_plan_t plan, const void *d_in, void *d_out
                                size_t workspace_bytes, void *hip_stream, mclahe_timer_t timer);
 mclahe_status mclahe_timer_read(mclahe_timer_t timer, float *pass_ms, int *runs);
 
+/* Contrast metrics (the paper's Sec. II measures, used in Tables I and II to
+ * judge enhancement): for a volume x, and optionally a second volume y of the
+ * same voxel count (e.g. an enhanced result) judged against x:
+ *   - lo, hi: minimum and maximum; each volume is min-max normalised to
+ *     u = (v - lo) / (hi - lo) in [0, 1] (u = 0 where hi == lo) first;
+ *   - mean and std: mean and population standard deviation (RMS contrast)
+ *     of u;
+ *   - entropy: Shannon entropy in bits, -sum p_j log2 p_j, of the n_bins-bin
+ *     grey-level histogram of the raw values over [lo, hi], binned as the
+ *     CLAHE histograms are (single precision: t = (v - lo) * (n_bins /
+ *     (hi - lo)), bin = t > 0 ? min(floor(t), n_bins - 1) : 0);
+ *   - mse = mean((u_x - u_y)^2) and psnr = 10 log10(peak^2 / mse) dB (+inf
+ *     for mse = 0).  Both tables of the paper follow from peak = 2^23.
+ * Sums are accumulated in double; results are reproducible bit for bit.
+ * Without y (d_y = NULL), the [1] entries, mse and psnr are 0.
+ * d_x, d_y: device arrays of nvox >= 1 elements of their dtypes, finite
+ * values.  d_result: device pointer to one mclahe_metrics_result (written
+ * when the stream reaches the last launch).  d_hist: optional device array
+ * of 2 * n_bins uint64 receiving the histogram counts of x then y (NULL:
+ * not written).  d_workspace: device, 256-byte aligned, at least
+ * mclahe_metrics_workspace_size() bytes; owned by the caller, clobbered.
+ * Asynchronous on hip_stream (four launches, no synchronisation).
+ * Errors: INVALID_VALUE for nvox < 1, n_bins outside [2, 8192], NULL x or
+ * result, an unknown dtype or a peak not positive and finite; WORKSPACE for
+ * a small or misaligned workspace. */
+typedef struct {
+    double lo[2], hi[2];   /* minimum and maximum of x ([0]) and y ([1])      */
+    double mean[2];        /* mean of the normalised volume                  */
+    double std[2];         /* population standard deviation of it            */
+    double entropy[2];     /* grey-level Shannon entropy in bits             */
+    double mse;            /* mean squared difference of the normalised x, y */
+    double psnr;           /* 10 log10(peak^2 / mse) in dB                    */
+    uint64_t count;        /* voxels per volume                               */
+} mclahe_metrics_result;
+mclahe_status mclahe_metrics_workspace_size(int64_t nvox, int n_bins, size_t *bytes);
+mclahe_status mclahe_metrics(const void *d_x, mclahe_dtype x_dtype, const void *d_y, mclahe_dtype y_dtype,
+                             int64_t nvox, int n_bins, double peak, mclahe_metrics_result *d_result,
+                             uint64_t *d_hist, void *d_workspace, size_t workspace_bytes, void *hip_stream);
+
 /* Human-readable name of a status code (static storage).                   */
 const char *mclahe_status_string(mclahe_status s);
 

@@ -5,7 +5,8 @@ Eqs. 1-2, Sec. III.C and III.D of Stimper et al., "Multidimensional Contrast
 Limited Adaptive Histogram Equalization", 2019), loaded with ctypes.  Only the
 tests, the smoke check and the CPU-baseline leg of the benchmark may import
 this package; the product library never does, and this package never imports
-the product.
+the product.  The contrast metrics the paper judges its results by are stated
+separately, in plain numpy, in ``oracle/metrics.py``.
 """
 from __future__ import annotations
 

@@ -48,6 +48,20 @@ class Tuning(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class MetricsResult(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 2), ("hi", ctypes.c_double * 2), ("mean", ctypes.c_double * 2),
+                ("std", ctypes.c_double * 2), ("entropy", ctypes.c_double * 2), ("mse", ctypes.c_double),
+                ("psnr", ctypes.c_double), ("count", ctypes.c_uint64)]
+
+    def as_dict(self, two: bool) -> dict:
+        k = 2 if two else 1
+        d = {n: list(getattr(self, n))[:k] for n in ("lo", "hi", "mean", "std", "entropy")}
+        if two:
+            d["mse"], d["psnr"] = self.mse, self.psnr
+        d["count"] = self.count
+        return d
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1906_11355_amd.build`")
@@ -90,6 +104,9 @@ def _load():
         "mclahe_timer_reset": [P],
         "mclahe_run_timed": [P, P, P, P, ctypes.c_size_t, P, P],
         "mclahe_timer_read": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int)],
+        "mclahe_metrics_workspace_size": [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_metrics": [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                           P, P, P, ctypes.c_size_t, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -295,6 +312,19 @@ def batched_table(plans, d_ins, d_outs, d_ws: int) -> bytes:
     _check(lib.mclahe_batched_table(n, _plans_array(plans), ins, outs, d_ws, buf, need.value,
                                     ctypes.byref(need)))
     return buf.raw
+
+
+def metrics_workspace_size(nvox: int, n_bins: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.mclahe_metrics_workspace_size(int(nvox), int(n_bins), ctypes.byref(n)))
+    return n.value
+
+
+def metrics_ptr(d_x: int, x_code: int, d_y, y_code: int, nvox: int, n_bins: int, peak: float,
+                d_result: int, d_hist, d_ws: int, ws_bytes: int, stream: int = 0):
+    """mclahe_metrics: d_result receives one MetricsResult (device memory)."""
+    _check(lib.mclahe_metrics(d_x, int(x_code), d_y, int(y_code), int(nvox), int(n_bins), float(peak),
+                              d_result, d_hist, d_ws, ws_bytes, stream))
 
 
 def version() -> str:

@@ -5,6 +5,7 @@ library's HIP kernels through the C ABI (see ``_lib``).
 """
 from __future__ import annotations
 
+import ctypes
 from typing import Sequence
 
 import torch
@@ -101,3 +102,33 @@ def autotune(plan: Plan, x: torch.Tensor, out: torch.Tensor | None = None):
         out = torch.empty(x.shape, dtype=TORCH_DTYPE[plan.out_code], device=x.device)
     plan.autotune_ptr(x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), stream_handle(x.device))
     return plan.tuning()
+
+
+def metrics(x: torch.Tensor, y: torch.Tensor | None = None, n_bins: int = 256, peak: float = 1.0,
+            workspace: torch.Tensor | None = None, with_hist: bool = False) -> dict:
+    """Contrast metrics of x, and of y against x (MSE, PSNR, STD, entropy).
+
+    Runs the library's metric kernels on the current stream and waits for the
+    result (a few dozen bytes copied back).
+    """
+    _check_tensor(x, "x")
+    if y is not None:
+        _check_tensor(y, "y")
+        if y.numel() != x.numel():
+            raise ValueError("x and y must have the same number of voxels")
+    n = x.numel()
+    need = _lib.metrics_workspace_size(n, n_bins)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    res = torch.empty(ctypes.sizeof(_lib.MetricsResult), dtype=torch.uint8, device=x.device)
+    hist = torch.empty(2 * n_bins, dtype=torch.int64, device=x.device) if with_hist else None
+    _lib.metrics_ptr(x.data_ptr(), _lib.dtype_code(x.dtype), None if y is None else y.data_ptr(),
+                     _lib.dtype_code(y.dtype) if y is not None else 0, n, n_bins, peak, res.data_ptr(),
+                     None if hist is None else hist.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                     stream_handle(x.device))
+    r = _lib.MetricsResult.from_buffer_copy(bytes(res.cpu().numpy()))
+    out = r.as_dict(y is not None)
+    if with_hist:
+        h = hist.cpu().numpy()
+        out["hist"] = [h[:n_bins], h[n_bins:]] if y is not None else [h[:n_bins]]
+    return out

@@ -2,6 +2,11 @@
 // units of the MCLAHE library.
 #pragma once
 #include "mc_desc.h"
+#include "../../include/mclahe.h"
+
+// Thread-local error message of the C ABI (set by a failing call).
+mclahe_status mc_fail(mclahe_status s, const char *fmt, ...);
+void mc_clear_error();
 
 typedef void (*KFn)(McVol);         // per-volume kernel: one volume by value
 typedef void (*KFnB)(McBatchSrc);   // batched twin: many volumes of one class

@@ -40,6 +40,19 @@ static mclahe_status fail(mclahe_status s, const char *fmt, ...)
     return s;
 }
 
+mclahe_status mc_fail(mclahe_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+void mc_clear_error() { g_err.clear(); }
+
 #define HIPCHK(call)                                                                     \
     do {                                                                                 \
         hipError_t e_ = (call);                                                          \

@@ -329,3 +329,46 @@ def test_batched_table_decodes_every_unit_once():
         assert ptrs[3 * i] == ins[i] and ptrs[3 * i + 1] == outs[i]
         assert ptrs[3 * i + 2] == ws + offs[i] + p.layout()["hist"]
     assert counts[0 * n + n - 1] == 0                              # user range: no range pass
+
+
+# ---------------------------------------------------------------- metrics --
+def test_metrics_workspace_size():
+    small = _lib.metrics_workspace_size(1, 2)
+    assert small > 0 and small % 256 == 0
+    # grows with the bins (histogram counters) and with the work-groups, which
+    # saturate for large volumes
+    assert _lib.metrics_workspace_size(1, 8192) >= small + 2 * 8192 * 8 - 256
+    big = _lib.metrics_workspace_size(1 << 28, 256)
+    assert big == _lib.metrics_workspace_size(1 << 34, 256)
+    assert big > _lib.metrics_workspace_size(1000, 256)
+
+
+@pytest.mark.parametrize("nvox,nb", [(0, 256), (-5, 256), (100, 1), (100, 8193)])
+def test_metrics_workspace_size_rejects(nvox, nb):
+    with pytest.raises(MclaheError) as e:
+        _lib.metrics_workspace_size(nvox, nb)
+    assert e.value.status == _lib.INVALID_VALUE
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(x=None), _lib.INVALID_VALUE),
+    (dict(res=None), _lib.INVALID_VALUE),
+    (dict(xdt=7), _lib.INVALID_VALUE),
+    (dict(y=0x2000, ydt=9), _lib.INVALID_VALUE),
+    (dict(peak=0.0), _lib.INVALID_VALUE),
+    (dict(peak=float("inf")), _lib.INVALID_VALUE),
+    (dict(peak=float("nan")), _lib.INVALID_VALUE),
+    (dict(ws=None), _lib.WORKSPACE),
+    (dict(ws=0x1010), _lib.WORKSPACE),
+    (dict(wsb=16), _lib.WORKSPACE),
+    (dict(nvox=0), _lib.INVALID_VALUE),
+])
+def test_metrics_argument_checks(kw, status):
+    # every check runs before any device call: fake addresses are never touched
+    a = dict(x=0x1000, xdt=2, y=None, ydt=2, nvox=1000, nb=256, peak=1.0, res=0x3000, ws=0x4000,
+             wsb=1 << 20)
+    a.update(kw)
+    with pytest.raises(MclaheError) as e:
+        _lib.metrics_ptr(a["x"], a["xdt"], a["y"], a["ydt"], a["nvox"], a["nb"], a["peak"], a["res"], None,
+                         a["ws"], a["wsb"], 0)
+    assert e.value.status == status
