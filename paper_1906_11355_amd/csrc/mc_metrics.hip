@@ -11,8 +11,12 @@
 //           the histogram counters;
 //   accum : per voxel, float64 squared deviations from the normalised mean
 //           and the squared difference of the two normalised volumes; LDS
-//           grey-level histograms (one wavefront-aggregated round for the
-//           most common bin) flushed into 64-bit counters;
+//           grey-level histograms flushed into 64-bit counters.  Raw data
+//           pile up on a few grey levels, and lanes of one wavefront adding
+//           to one LDS word serialise: the lanes sharing the first lane's
+//           bin add once, and every bin has R lane-interleaved copies
+//           (lane l adds to copy l mod R) in consecutive words, i.e.
+//           different banks;
 //   final : reduces the partial sums in a fixed order and writes the result.
 // The grid and the per-thread order are fixed, so results are reproducible
 // bit for bit from run to run.
@@ -32,6 +36,8 @@ constexpr int kT = 256;          // threads per work-group (4 wavefronts)
 constexpr int kChunk = 8;        // elements per thread and step
 constexpr int kMaxGroups = 2048; // 8 work-groups per compute unit
 constexpr int kMaxBins = 8192;   // two LDS histograms of this many u32: 64 KiB
+constexpr int kMaxCopies = 4;    // lane-interleaved copies of each bin
+constexpr size_t kCopyLds = 32 * 1024;   // LDS the copies may take
 
 struct RangePart {      // one per work-group of the range pass
     float mn[2], mx[2];
@@ -226,33 +232,35 @@ __device__ __forceinline__ uint32_t met_bin(float v, float lo, float scale, uint
     return min(__float2uint_rz(t), nbm1);
 }
 
-// Count bin b of every active lane: the lanes sharing the first active
-// lane's bin add once, with their number; the others add one each.
-__device__ __forceinline__ void count_bin(uint32_t *h, uint32_t b)
+// Count bin b of every active lane in copy (lane mod R) of an LDS histogram
+// laid out [bin][R] (rs = log2 R): the lanes sharing the first active lane's
+// bin add once, with their number; the others add one each.
+__device__ __forceinline__ void count_bin(uint32_t *h, uint32_t b, int rs)
 {
+    const uint32_t lane = threadIdx.x & 63, cm = (1u << rs) - 1u;
     const uint32_t lead = __builtin_amdgcn_readfirstlane(b);
     const unsigned long long same = __ballot(b == lead);
     if (b == lead) {
-        if ((int)(threadIdx.x & 63) == (int)__ffsll((long long)same) - 1)
-            atomicAdd(&h[lead], (uint32_t)__popcll(same));
+        if ((int)lane == (int)__ffsll((long long)same) - 1)
+            atomicAdd(&h[(lead << rs) + (lane & cm)], (uint32_t)__popcll(same));
     } else {
-        atomicAdd(&h[b], 1u);
+        atomicAdd(&h[(b << rs) + (lane & cm)], 1u);
     }
 }
 
 // ---------------------------------------------------------------- accum --
 template <typename TX, typename TY, bool VEC>
-__global__ void __launch_bounds__(kT) k_met_accum(const TX *x, const TY *y, int64_t nvox, int nb,
+__global__ void __launch_bounds__(kT) k_met_accum(const TX *x, const TY *y, int64_t nvox, int nb, int rs,
                                                  const Stats *stp, AccPart *part,
                                                  unsigned long long *hist)
 {
     constexpr bool HY = !std::is_same<TY, None>::value;
-    extern __shared__ uint32_t lh[];     // [nv][nb]; reused for the sums
-    const int nv = HY ? 2 : 1;
-    for (int i = threadIdx.x; i < nv * nb; i += kT) lh[i] = 0u;
+    extern __shared__ uint32_t lh[];     // [nv][nb][R]; reused for the sums
+    const int nv = HY ? 2 : 1, R = 1 << rs;
+    for (int i = threadIdx.x; i < nv * nb * R; i += kT) lh[i] = 0u;
     const Stats st = *stp;
     const uint32_t nbm1 = (uint32_t)nb - 1;
-    uint32_t *hy = lh + nb;
+    uint32_t *hy = lh + nb * R;
     __syncthreads();
     double sxx = 0.0, syy = 0.0, sdd = 0.0;
     const int64_t nch = nvox / kChunk, stride = (int64_t)gridDim.x * kT;
@@ -260,13 +268,13 @@ __global__ void __launch_bounds__(kT) k_met_accum(const TX *x, const TY *y, int6
     auto voxel = [&](float a, float b) {
         const double cx = fma((double)a, st.inv[0], st.off[0]);
         sxx = fma(cx, cx, sxx);
-        count_bin(lh, met_bin(a, st.lo[0], st.scale[0], nbm1));
+        count_bin(lh, met_bin(a, st.lo[0], st.scale[0], nbm1), rs);
         if constexpr (HY) {
             const double cy = fma((double)b, st.inv[1], st.off[1]);
             syy = fma(cy, cy, syy);
             const double d = (cx - cy) + st.dmean;
             sdd = fma(d, d, sdd);
-            count_bin(hy, met_bin(b, st.lo[1], st.scale[1], nbm1));
+            count_bin(hy, met_bin(b, st.lo[1], st.scale[1], nbm1), rs);
         }
     };
     for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < nch; c += stride) {
@@ -286,8 +294,11 @@ __global__ void __launch_bounds__(kT) k_met_accum(const TX *x, const TY *y, int6
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nv * nb; i += kT)
-        if (lh[i]) atomicAdd(&hist[i], (unsigned long long)lh[i]);
+    for (int i = threadIdx.x; i < nv * nb; i += kT) {
+        uint32_t c = 0;
+        for (int r = 0; r < R; ++r) c += lh[i * R + r];
+        if (c) atomicAdd(&hist[i], (unsigned long long)c);
+    }
     double *red = reinterpret_cast<double *>(lh);   // group_sum waits for the flush
     const double a = group_sum(sxx, red);
     double b = 0.0, d = 0.0;
@@ -385,9 +396,11 @@ mclahe_status launch_passes(const void *x, const void *y, int64_t nvox, int nb, 
     hipLaunchKernelGGL((k_met_range<TX, TY, VEC>), dim3(g), dim3(kT), 0, st, (const TX *)x, (const TY *)y, nvox,
                        rp);
     hipLaunchKernelGGL(k_met_stats, dim3(1), dim3(kT), 0, st, rp, g, nv, nvox, nb, sp, h);
-    const size_t lds = std::max(sizeof(uint32_t) * nv * nb, 4 * sizeof(double));
+    int rs = 0;   // copies per bin: as many as fit the LDS budget, at most 4
+    while ((2 << rs) <= kMaxCopies && sizeof(uint32_t) * nv * nb * (2 << rs) <= kCopyLds) ++rs;
+    const size_t lds = std::max(sizeof(uint32_t) * nv * nb * (1 << rs), 4 * sizeof(double));
     hipLaunchKernelGGL((k_met_accum<TX, TY, VEC>), dim3(g), dim3(kT), lds, st,
-                       (const TX *)x, (const TY *)y, nvox, nb, sp, ap, h);
+                       (const TX *)x, (const TY *)y, nvox, nb, rs, sp, ap, h);
     hipLaunchKernelGGL(k_met_final, dim3(1), dim3(kT), 0, st, ap, g, nv, nvox, nb, peak, sp, h, res,
                        hist_out);
     const hipError_t e = hipGetLastError();
