@@ -6,7 +6,8 @@ Limited Adaptive Histogram Equalization", 2019), loaded with ctypes.  Only the
 tests, the smoke check and the CPU-baseline leg of the benchmark may import
 this package; the product library never does, and this package never imports
 the product.  The contrast metrics the paper judges its results by are stated
-separately, in plain numpy, in ``oracle/metrics.py``.
+separately, in plain numpy, in ``oracle/metrics.py``, and the pre-denoising
+filters of the paper's experiments in ``oracle/denoise.py``.
 """
 from __future__ import annotations
 
@@ -35,6 +36,8 @@ def build(force: bool = True) -> str:
                "-fno-fast-math", "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
+    from . import denoise
+    denoise.build(force)
     return _LIB
 
 
