@@ -308,6 +308,46 @@ mclahe_status mclahe_metrics(const void *d_x, mclahe_dtype x_dtype, const void *
                              int64_t nvox, int n_bins, double peak, mclahe_metrics_result *d_result,
                              uint64_t *d_hist, void *d_workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Pre-denoising filters of the paper's experiments (Sec. IV): the
+ * photoemission volume is smoothed by a Gaussian filter with a standard
+ * deviation per axis, the microscopy volume by a median filter over a
+ * (2, 2, 2, 1) window, before CLAHE.  Both take C-contiguous device arrays
+ * of ndim (1..8) axes; input and output must not overlap.  Outside the array
+ * the data continue by edge-repeating reflection ([a b c] -> [.. b a | a b c
+ * | c b ..], repeated for windows longer than the axis), as in the CLAHE
+ * padding.
+ *
+ * mclahe_gaussian: separable; one pass per axis with sigma[i] > 0, axes in
+ * order 0..ndim-1 (sigma[i] = 0 leaves axis i alone).  Radius
+ * r = (int)(truncate * sigma + 0.5) (truncate 4 is the common choice; r at
+ * most 64); weights exp(-0.5 / sigma^2 * j^2) for j = -r..r divided by
+ * their sum, in double, rounded to float.  Each output of a pass is the
+ * single-precision fused multiply-add chain over j = -r..r starting from 0,
+ * so results are reproducible bit for bit.  Input u8, u16 or f32; output
+ * f32.  With two or more axes to smooth, a workspace of
+ * mclahe_gaussian_workspace_size() bytes (one float volume, device,
+ * 256-byte aligned, must not overlap the output) holds the intermediate
+ * passes; otherwise it may be NULL.  Asynchronous on hip_stream.
+ * Errors: INVALID_VALUE for a bad shape, NULL buffers, an unknown dtype, a
+ * negative or non-finite sigma or truncate, or overlapping buffers;
+ * NOT_SUPPORTED for a radius over 64; WORKSPACE for a small or misaligned
+ * workspace.
+ *
+ * mclahe_median: window[i] >= 1 samples along axis i at offsets
+ * -(window[i] / 2) .. window[i] - 1 - window[i] / 2 (for 2: the sample and
+ * its predecessor); the output is the window value of rank N / 2 (0-based,
+ * ascending), N = prod window[i] <= 64: the median for odd N, the upper of
+ * the two middle values for even N.  Output in the input dtype, exact.
+ * Asynchronous on hip_stream.  Errors: INVALID_VALUE for a bad shape or
+ * window, NULL buffers, an unknown dtype or overlapping buffers;
+ * NOT_SUPPORTED for N > 64. */
+mclahe_status mclahe_gaussian_workspace_size(int ndim, const int64_t *shape, const double *sigma, size_t *bytes);
+mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim, const int64_t *shape,
+                              const double *sigma, double truncate, float *d_out, void *d_workspace,
+                              size_t workspace_bytes, void *hip_stream);
+mclahe_status mclahe_median(const void *d_in, mclahe_dtype dtype, int ndim, const int64_t *shape,
+                            const int32_t *window, void *d_out, void *hip_stream);
+
 /* Human-readable name of a status code (static storage).                   */
 const char *mclahe_status_string(mclahe_status s);
 

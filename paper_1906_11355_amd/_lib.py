@@ -105,6 +105,11 @@ def _load():
         "mclahe_run_timed": [P, P, P, P, ctypes.c_size_t, P, P],
         "mclahe_timer_read": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int)],
         "mclahe_metrics_workspace_size": [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_gaussian_workspace_size": [ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_gaussian": [P, ctypes.c_int, ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                            P, P, ctypes.c_size_t, P],
+        "mclahe_median": [P, ctypes.c_int, ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_int32), P, P],
         "mclahe_metrics": [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                            P, P, P, ctypes.c_size_t, P],
     }
@@ -325,6 +330,35 @@ def metrics_ptr(d_x: int, x_code: int, d_y, y_code: int, nvox: int, n_bins: int,
     """mclahe_metrics: d_result receives one MetricsResult (device memory)."""
     _check(lib.mclahe_metrics(d_x, int(x_code), d_y, int(y_code), int(nvox), int(n_bins), float(peak),
                               d_result, d_hist, d_ws, ws_bytes, stream))
+
+
+def _shape_sigma(shape, sigma):
+    D = len(shape)
+    sh = (ctypes.c_int64 * D)(*[int(v) for v in shape])
+    sg = (ctypes.c_double * D)(*[float(v) for v in sigma])
+    return D, sh, sg
+
+
+def gaussian_workspace_size(shape, sigma) -> int:
+    D, sh, sg = _shape_sigma(shape, sigma)
+    n = ctypes.c_size_t()
+    _check(lib.mclahe_gaussian_workspace_size(D, sh, sg, ctypes.byref(n)))
+    return n.value
+
+
+def gaussian_ptr(d_in: int, in_code: int, shape, sigma, truncate: float, d_out: int, d_ws, ws_bytes: int,
+                 stream: int = 0):
+    """mclahe_gaussian: separable Gaussian smoothing into a float32 array."""
+    D, sh, sg = _shape_sigma(shape, sigma)
+    _check(lib.mclahe_gaussian(d_in, int(in_code), D, sh, sg, float(truncate), d_out, d_ws, ws_bytes, stream))
+
+
+def median_ptr(d_in: int, code: int, shape, window, d_out: int, stream: int = 0):
+    """mclahe_median: median filter, output in the input dtype."""
+    D = len(shape)
+    sh = (ctypes.c_int64 * D)(*[int(v) for v in shape])
+    win = (ctypes.c_int32 * D)(*[int(v) for v in window])
+    _check(lib.mclahe_median(d_in, int(code), D, sh, win, d_out, stream))
 
 
 def version() -> str:

@@ -132,3 +132,32 @@ def metrics(x: torch.Tensor, y: torch.Tensor | None = None, n_bins: int = 256, p
         h = hist.cpu().numpy()
         out["hist"] = [h[:n_bins], h[n_bins:]] if y is not None else [h[:n_bins]]
     return out
+
+
+def gaussian(x: torch.Tensor, sigma, truncate: float = 4.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Separable Gaussian smoothing (one sigma per axis, 0 = leave the axis) into float32."""
+    _check_tensor(x, "input")
+    sigma = [float(s) for s in (sigma if hasattr(sigma, "__len__") else [sigma] * x.dim())]
+    if len(sigma) != x.dim():
+        raise ValueError("one sigma per axis")
+    if out is None:
+        out = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    _check_tensor(out, "output")
+    need = _lib.gaussian_workspace_size(x.shape, sigma)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    _lib.gaussian_ptr(x.data_ptr(), _lib.dtype_code(x.dtype), x.shape, sigma, truncate, out.data_ptr(),
+                      ws.data_ptr() if need else None, need, stream_handle(x.device))
+    return out
+
+
+def median(x: torch.Tensor, window, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Median filter over a window per axis (even sizes: upper middle value)."""
+    _check_tensor(x, "input")
+    if len(window) != x.dim():
+        raise ValueError("one window size per axis")
+    if out is None:
+        out = torch.empty_like(x)
+    _check_tensor(out, "output")
+    _lib.median_ptr(x.data_ptr(), _lib.dtype_code(x.dtype), x.shape, window, out.data_ptr(),
+                    stream_handle(x.device))
+    return out

@@ -372,3 +372,50 @@ def test_metrics_argument_checks(kw, status):
         _lib.metrics_ptr(a["x"], a["xdt"], a["y"], a["ydt"], a["nvox"], a["nb"], a["peak"], a["res"], None,
                          a["ws"], a["wsb"], 0)
     assert e.value.status == status
+
+
+# -------------------------------------------------------------- denoising --
+def test_gaussian_workspace_size():
+    assert _lib.gaussian_workspace_size((10, 20), (0.0, 1.0)) == 0          # one pass: none
+    assert _lib.gaussian_workspace_size((10, 20), (0.7, 1.0)) == 1024      # 200 floats, 256-aligned
+    assert _lib.gaussian_workspace_size((256, 256, 128, 32), (0.7, 0.7, 0.9, 1.3)) == 4 * 256 * 256 * 128 * 32
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(shape=(0, 4)), _lib.INVALID_VALUE),
+    (dict(shape=(2,) * 9, sigma=(1.0,) * 9), _lib.INVALID_VALUE),
+    (dict(sigma=(-1.0, 1.0)), _lib.INVALID_VALUE),
+    (dict(sigma=(float("nan"), 1.0)), _lib.INVALID_VALUE),
+    (dict(sigma=(20.0, 1.0)), _lib.NOT_SUPPORTED),
+    (dict(truncate=0.0), _lib.INVALID_VALUE),
+    (dict(code=5), _lib.INVALID_VALUE),
+    (dict(src=None), _lib.INVALID_VALUE),
+    (dict(dst=0x100010), _lib.INVALID_VALUE),          # overlaps the input
+    (dict(ws=None), _lib.WORKSPACE),
+    (dict(ws=0x900010), _lib.WORKSPACE),
+    (dict(wsb=8), _lib.WORKSPACE),
+])
+def test_gaussian_argument_checks(kw, status):
+    a = dict(shape=(16, 16), sigma=(0.7, 1.3), truncate=4.0, code=2, src=0x100000, dst=0x800000,
+             ws=0x900000, wsb=1 << 20)
+    a.update(kw)
+    with pytest.raises(MclaheError) as e:
+        _lib.gaussian_ptr(a["src"], a["code"], a["shape"], a["sigma"], a["truncate"], a["dst"], a["ws"],
+                          a["wsb"], 0)
+    assert e.value.status == status
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(shape=(4, 0)), _lib.INVALID_VALUE),
+    (dict(window=(0, 2)), _lib.INVALID_VALUE),
+    (dict(window=(9, 8)), _lib.NOT_SUPPORTED),
+    (dict(code=3), _lib.INVALID_VALUE),
+    (dict(dst=0x100004), _lib.INVALID_VALUE),
+    (dict(dst=None), _lib.INVALID_VALUE),
+])
+def test_median_argument_checks(kw, status):
+    a = dict(shape=(16, 16), window=(2, 2), code=0, src=0x100000, dst=0x800000)
+    a.update(kw)
+    with pytest.raises(MclaheError) as e:
+        _lib.median_ptr(a["src"], a["code"], a["shape"], a["window"], a["dst"], 0)
+    assert e.value.status == status
