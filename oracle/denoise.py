@@ -120,3 +120,17 @@ def median(x: np.ndarray, size) -> np.ndarray:
     stack = np.stack(views, axis=0)
     N = stack.shape[0]
     return np.sort(stack, axis=0)[N // 2].astype(x.dtype)
+
+
+def median_at(x: np.ndarray, size, points: np.ndarray) -> np.ndarray:
+    """The median filter's output at the given coordinates only ([m, ndim])."""
+    x = np.asarray(x)
+    size = [int(k) for k in size]
+    pts = np.asarray(points, dtype=np.int64)
+    offsets = [range(-(k // 2), k - k // 2) for k in size]
+    vals = []
+    for off in itertools.product(*offsets):
+        idx = tuple(reflect_index(pts[:, a] + o, n) for a, (n, o) in enumerate(zip(x.shape, off)))
+        vals.append(x[idx])
+    stack = np.stack(vals, axis=0)
+    return np.sort(stack, axis=0)[stack.shape[0] // 2].astype(x.dtype)

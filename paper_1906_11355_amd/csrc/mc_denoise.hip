@@ -9,16 +9,21 @@
 // reflection outside the array (the CLAHE padding, period 2n); every output
 // is the float32 fused multiply-add chain over j = -r..r starting from 0, so
 // the result is bit-identical to a plain loop that does the same.
-//   - last axis (contiguous): a work-group stages a flat tile of 2048 outputs
-//     plus r halo samples on each side in LDS (reflection never reaches
-//     further than r from an output) and every thread filters 8 outputs;
+//   - last axis (contiguous), rows of up to 2048 samples: a work-group stages
+//     whole rows in LDS, each with its r reflected halo samples on both
+//     sides, and every output reads its taps at fixed offsets;
+//   - longer rows: a flat tile of 2048 outputs plus r halo samples on each
+//     side (reflection never reaches further than r from an output);
 //   - any other axis (stride S): a thread owns 4 (or 1) adjacent columns and
 //     sweeps a segment of the axis with a ring of 2r + 1 samples in
 //     registers, unrolled by the ring length so that every slot index is a
 //     compile-time constant: each input is loaded once per segment.
-// Median: one output per thread; the window's values are gathered with
-// reflected coordinates and sorted by a bitonic network padded to a power
-// of two; the value of rank N / 2 (0-based) is written in the input dtype.
+// Median: values become order-preserving unsigned keys (integer min/max);
+// a bitonic network padded to a power of two sorts them and the key of rank
+// N / 2 (0-based) is written back in the input dtype.  Two launches: outputs
+// whose window lies inside the array (4 consecutive outputs of a row per
+// thread where the window allows, values gathered at precomputed flat
+// offsets), then the border slabs (coordinates reflected per value).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,35 +62,135 @@ __device__ __forceinline__ float ld1(const T *p, int64_t i)
 }
 
 // ------------------------------------------------------------- last axis --
-template <typename T>
+// Taps of output position p (of a row of n) whose window crosses a row end:
+// one reflection suffices while r < n, repeated reflection otherwise.
+__device__ __forceinline__ int tap_pos(int q, int n, bool single)
+{
+    if (single) {
+        q = q < 0 ? -q - 1 : q;
+        return q >= n ? 2 * n - 1 - q : q;
+    }
+    return (int)refl(q, n);
+}
+
+// RT > 0: the radius as a compile-time constant (taps unrolled, weights in
+// registers); RT = 0: any radius r.
+template <typename T, int RT>
 __global__ void __launch_bounds__(kT) k_gauss_last(const T *in, float *out, int64_t nvox, int64_t n, int r,
                                                   Weights W)
 {
+    if constexpr (RT > 0) r = RT;
     extern __shared__ float tile[];   // [kTile + 2r]
     const int64_t e0 = (int64_t)blockIdx.x * kTile;
     const int64_t lo = e0 - r;
     const int len = kTile + 2 * r;
-    for (int i = threadIdx.x; i < len; i += kT) {
-        const int64_t e = lo + i;
-        tile[i] = (e >= 0 && e < nvox) ? ld1(in, e) : 0.f;
+    {
+        float v[kTile / kT];          // all of a thread's loads in flight at once
+#pragma unroll
+        for (int k = 0; k < kTile / kT; ++k) {
+            const int64_t e = lo + threadIdx.x + k * kT;
+            v[k] = (e >= 0 && e < nvox) ? ld1(in, e) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < kTile / kT; ++k) tile[threadIdx.x + k * kT] = v[k];
+        for (int i = kTile + threadIdx.x; i < len; i += kT) {
+            const int64_t e = lo + i;
+            tile[i] = (e >= 0 && e < nvox) ? ld1(in, e) : 0.f;
+        }
+    }
+    float w[RT > 0 ? 2 * RT + 1 : 1];
+    if constexpr (RT > 0) {
+#pragma unroll
+        for (int j = 0; j <= 2 * RT; ++j) w[j] = W.w[j];
     }
     __syncthreads();
+    // position in its row of the thread's first output, then stepped by kT
+    // (all 32-bit: rows of up to 2^30 samples)
+    const int nn = (int)n;
+    const int step = kT % nn;
+    int p = (int)((e0 + threadIdx.x) % n);
+    const bool single = r < nn;
 #pragma unroll 2
     for (int k = 0; k < kTile / kT; ++k) {
         const int t = threadIdx.x + k * kT;
         const int64_t e = e0 + t;
         if (e >= nvox) break;
-        const int64_t p = e % n;
         float acc = 0.f;
-        if (p >= r && p + r < n) {
-            for (int j = -r; j <= r; ++j) acc = __builtin_fmaf(W.w[j + r], tile[t + r + j], acc);
+        if (p >= r && p + r < nn) {
+            if constexpr (RT > 0) {
+#pragma unroll
+                for (int j = 0; j <= 2 * RT; ++j) acc = __builtin_fmaf(w[j], tile[t + j], acc);
+            } else {
+                for (int j = 0; j <= 2 * r; ++j) acc = __builtin_fmaf(W.w[j], tile[t + j], acc);
+            }
         } else {
+            // same row, within r of e: tile index t + r + (q - p)
             for (int j = -r; j <= r; ++j) {
-                const int64_t q = e - p + refl(p + j, n);   // same row, within r of e
-                acc = __builtin_fmaf(W.w[j + r], tile[(int)(q - lo)], acc);
+                const int q = tap_pos(p + j, nn, single);
+                acc = __builtin_fmaf(W.w[j + r], tile[t + r + q - p], acc);
             }
         }
         out[e] = acc;
+        p += step;
+        if (p >= nn) p -= nn;
+    }
+}
+
+// Short rows (n <= kTile): a work-group stages whole rows, each with its r
+// reflected halo samples on both sides, so that every output reads its taps
+// at fixed offsets (no per-output reflection, no divergence at row ends).
+template <typename T, int RT>
+__global__ void __launch_bounds__(kT) k_gauss_rows(const T *in, float *out, int64_t nvox, int n, int r,
+                                                  int rows_per_group, Weights W)
+{
+    if constexpr (RT > 0) r = RT;
+    extern __shared__ float rowbuf[];   // [rows][n + 2r]
+    const int rs = n + 2 * r;
+    const int64_t e0 = (int64_t)blockIdx.x * rows_per_group * n;
+    const int cnt = (int)std::min<int64_t>((int64_t)rows_per_group * n, nvox - e0);
+    const int dr = kT / n, dp = kT % n;
+    {
+        int row = threadIdx.x / n, p = threadIdx.x % n;
+        for (int i = threadIdx.x; i < cnt; i += kT) {
+            rowbuf[row * rs + r + p] = ld1(in, e0 + i);
+            row += dr;
+            p += dp;
+            if (p >= n) {
+                p -= n;
+                ++row;
+            }
+        }
+    }
+    __syncthreads();
+    const int rows = cnt / n;
+    for (int h = threadIdx.x; h < rows * 2 * r; h += kT) {
+        const int row = h / (2 * r), sl = h - row * 2 * r;
+        const int q = sl < r ? sl - r : n + (sl - r);          // position of the halo slot
+        rowbuf[row * rs + r + q] = rowbuf[row * rs + r + tap_pos(q, n, r < n)];
+    }
+    __syncthreads();
+    float w[RT > 0 ? 2 * RT + 1 : 1];
+    if constexpr (RT > 0) {
+#pragma unroll
+        for (int j = 0; j <= 2 * RT; ++j) w[j] = W.w[j];
+    }
+    int row = threadIdx.x / n, p = threadIdx.x % n;
+    for (int i = threadIdx.x; i < cnt; i += kT) {
+        const float *src = rowbuf + row * rs + p;   // taps p - r .. p + r
+        float acc = 0.f;
+        if constexpr (RT > 0) {
+#pragma unroll
+            for (int j = 0; j <= 2 * RT; ++j) acc = __builtin_fmaf(w[j], src[j], acc);
+        } else {
+            for (int j = 0; j <= 2 * r; ++j) acc = __builtin_fmaf(W.w[j], src[j], acc);
+        }
+        out[e0 + i] = acc;
+        row += dr;
+        p += dp;
+        if (p >= n) {
+            p -= n;
+            ++row;
+        }
     }
 }
 
@@ -148,11 +253,17 @@ __global__ void __launch_bounds__(kT) k_gauss_ring(const T *in, float *out, Cols
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) ring[j] = ldv<T, V>(in, base + refl(p0 - R + j, c.n) * c.S);
     for (int64_t pb = p0; pb < p1; pb += WN) {
+        // the chunk's WN new inputs are loaded back to back (all in flight),
+        // then moved into the ring as the outputs consume them
+        VecF<V> nxt[WN];
+#pragma unroll
+        for (int u = 0; u < WN; ++u)
+            if (pb + u < p1) nxt[u] = ldv<T, V>(in, base + refl(pb + u + R, c.n) * c.S);
 #pragma unroll
         for (int u = 0; u < WN; ++u) {
             const int64_t p = pb + u;
             if (p < p1) {
-                ring[(u + 2 * R) % WN] = ldv<T, V>(in, base + refl(p + R, c.n) * c.S);
+                ring[(u + 2 * R) % WN] = nxt[u];
                 float acc[V];
 #pragma unroll
                 for (int k = 0; k < V; ++k) acc[k] = 0.f;
@@ -203,10 +314,47 @@ struct MedGeom {
     int64_t shape[MC_MAXD], stride[MC_MAXD];
     int32_t lo[MC_MAXD], k[MC_MAXD]; // window offsets lo .. lo + k - 1 per axis
     int64_t nvox;
+    int64_t off[kMedianMax];         // flat offset of window value i (interior outputs)
+    int8_t woff[kMedianMax][MC_MAXD];  // per-axis offset of window value i
+    // border slabs: along axis a, positions [0, b0[a]) and [shape - b1[a], shape)
+    // (all positions if they meet), times every position of the other axes
+    int64_t b0[MC_MAXD], b1[MC_MAXD], slab_pre[MC_MAXD + 1];
 };
 
+// Order-preserving unsigned keys (integer min/max, no float canonicalising).
+template <typename T> __device__ __forceinline__ uint32_t key_of(T v) { return (uint32_t)v; }
+template <> __device__ __forceinline__ uint32_t key_of<float>(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+template <typename T> __device__ __forceinline__ T val_of(uint32_t k) { return (T)k; }
+template <> __device__ __forceinline__ float val_of<float>(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void ldk(const T *p, int64_t i, uint32_t (&k)[V])
+{
+    if constexpr (V == 4 && sizeof(T) == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(p + i);
+        k[0] = key_of<float>(a.x); k[1] = key_of<float>(a.y); k[2] = key_of<float>(a.z); k[3] = key_of<float>(a.w);
+    } else if constexpr (V == 4 && sizeof(T) == 2) {
+        const uint2 a = *reinterpret_cast<const uint2 *>(p + i);
+        k[0] = a.x & 0xffffu; k[1] = a.x >> 16; k[2] = a.y & 0xffffu; k[3] = a.y >> 16;
+    } else if constexpr (V == 4 && sizeof(T) == 1) {
+        const uint32_t a = *reinterpret_cast<const uint32_t *>(p + i);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = (a >> (8 * j)) & 0xffu;
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) k[j] = key_of<T>(p[i + j]);
+    }
+}
+
 template <int NP>
-__device__ __forceinline__ void bitonic_sort(float (&a)[NP])
+__device__ __forceinline__ void bitonic_sort(uint32_t (&a)[NP])
 {
 #pragma unroll
     for (int size = 2; size <= NP; size <<= 1)
@@ -217,45 +365,133 @@ __device__ __forceinline__ void bitonic_sort(float (&a)[NP])
                 const int j = i ^ stride;
                 if (j > i) {
                     const bool up = (i & size) == 0;
-                    const float x = a[i], y = a[j];
-                    a[i] = up ? fminf(x, y) : fmaxf(x, y);
-                    a[j] = up ? fmaxf(x, y) : fminf(x, y);
+                    const uint32_t x = a[i], y = a[j];
+                    a[i] = up ? min(x, y) : max(x, y);
+                    a[j] = up ? max(x, y) : min(x, y);
                 }
             }
 }
 
-template <typename T, int NP>
-__global__ void __launch_bounds__(kT) k_median(const T *in, T *out, MedGeom g)
+// Key of rank `rank` among NP keys (padding keys are all ones: they sort last).
+template <int NP, bool EXACT>
+__device__ __forceinline__ uint32_t rank_key(uint32_t (&v)[NP], int rank)
 {
-    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (e >= g.nvox) return;
-    int64_t pos[MC_MAXD];
-    int64_t rem = e;
-    for (int a = 0; a < g.D; ++a) {
-        pos[a] = rem / g.stride[a];
-        rem -= pos[a] * g.stride[a];
-    }
-    float v[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        v[i] = INFINITY;   // padding sorts last: the rank below N is unchanged
-        if (i < g.N) {
-            int q = i;
-            int64_t off = 0;
-            for (int a = g.D - 1; a >= 0; --a) {
-                const int o = q % g.k[a];
-                q /= g.k[a];
-                off += refl(pos[a] + g.lo[a] + o, g.shape[a]) * g.stride[a];
-            }
-            v[i] = (float)in[off];
-        }
-    }
     bitonic_sort<NP>(v);
-    float m = v[0];
+    if constexpr (EXACT) return v[NP / 2];
+    uint32_t m = v[0];
 #pragma unroll
     for (int i = 0; i < NP; ++i)
-        if (i == g.N / 2) m = v[i];
-    out[e] = (T)m;
+        if (i == rank) m = v[i];
+    return m;
+}
+
+template <typename T, int VM>
+__device__ __forceinline__ void stk(T *p, int64_t i, const uint32_t (&m)[VM])
+{
+    if constexpr (VM == 4 && sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(p + i) =
+            make_float4(val_of<float>(m[0]), val_of<float>(m[1]), val_of<float>(m[2]), val_of<float>(m[3]));
+    } else if constexpr (VM == 4 && sizeof(T) == 2) {
+        *reinterpret_cast<uint2 *>(p + i) = make_uint2(m[0] | (m[1] << 16), m[2] | (m[3] << 16));
+    } else if constexpr (VM == 4 && sizeof(T) == 1) {
+        *reinterpret_cast<uint32_t *>(p + i) = m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
+    } else {
+#pragma unroll
+        for (int j = 0; j < VM; ++j) p[i + j] = val_of<T>(m[j]);
+    }
+}
+
+// Outputs whose window lies inside the array: VM consecutive outputs of one
+// row per thread (VM = 4 needs a last-axis window of 1, a row length
+// divisible by 4 and aligned bases), window values gathered at precomputed
+// flat offsets.  Outputs near a border are left to k_median_border.  EXACT:
+// the window holds NP values.  IX: type of the coordinate arithmetic
+// (32-bit for arrays under 2^31 voxels).
+template <typename T, int NP, int VM, bool EXACT, typename IX>
+__global__ void __launch_bounds__(kT) k_median_interior(const T *in, T *out, MedGeom g)
+{
+    const int64_t e0 = ((int64_t)blockIdx.x * kT + threadIdx.x) * VM;
+    if (e0 >= g.nvox) return;
+    IX rem = (IX)e0;
+    bool interior = true;
+#pragma unroll
+    for (int a = 0; a < MC_MAXD; ++a)
+        if (a < g.D) {
+            const IX st = (IX)g.stride[a];
+            const IX pa = rem / st;
+            rem -= pa * st;
+            const int64_t q0 = (int64_t)pa + g.lo[a];
+            const int64_t q1 = q0 + g.k[a] - 1 + (a == g.D - 1 ? VM - 1 : 0);
+            interior = interior && (g.k[a] == 1 || (q0 >= 0 && q1 < g.shape[a]));
+        }
+    if (!interior) return;
+    uint32_t x[NP][VM];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        if (EXACT || i < g.N) ldk<T, VM>(in, e0 + g.off[i], x[i]);
+        else {
+#pragma unroll
+            for (int j = 0; j < VM; ++j) x[i][j] = 0xffffffffu;
+        }
+    }
+    uint32_t m[VM];
+#pragma unroll
+    for (int j = 0; j < VM; ++j) {
+        uint32_t v[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) v[i] = x[i][j];
+        m[j] = rank_key<NP, EXACT>(v, g.N / 2);
+    }
+    stk<T, VM>(out, e0, m);
+}
+
+// Outputs near a border: one per thread over the border slabs (a voxel on
+// several slabs is computed by each, with the same value), coordinates
+// reflected per window value.
+template <typename T, int NP>
+__global__ void __launch_bounds__(kT) k_median_border(const T *in, T *out, MedGeom g)
+{
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= g.slab_pre[g.D]) return;
+    int s = 0;
+#pragma unroll
+    for (int a = 1; a < MC_MAXD; ++a)
+        if (a < g.D && t >= g.slab_pre[a]) s = a;
+    // position along the slab axis, then the other axes from the rest
+    const int64_t per = g.nvox / g.shape[s];
+    int64_t l = t - g.slab_pre[s];
+    const int64_t bi = l / per;
+    l -= bi * per;
+    const int64_t cnt = g.b0[s] + g.b1[s];
+    const int64_t ps = cnt >= g.shape[s] ? bi : (bi < g.b0[s] ? bi : g.shape[s] - cnt + bi);
+    int64_t pos[MC_MAXD];
+    int64_t rest = l, e = 0;
+#pragma unroll
+    for (int a = MC_MAXD - 1; a >= 0; --a)
+        if (a < g.D) {
+            if (a == s) {
+                pos[a] = ps;
+            } else {
+                pos[a] = rest % g.shape[a];
+                rest /= g.shape[a];
+            }
+            e += pos[a] * g.stride[a];
+        } else {
+            pos[a] = 0;
+        }
+    uint32_t v[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        v[i] = 0xffffffffu;
+        if (i < g.N) {
+            int64_t off = 0;
+#pragma unroll
+            for (int a = 0; a < MC_MAXD; ++a)
+                if (a < g.D) off += refl(pos[a] + g.woff[i][a], g.shape[a]) * g.stride[a];
+            v[i] = key_of<T>(in[off]);
+        }
+    }
+    out[e] = val_of<T>(rank_key<NP, false>(v, g.N / 2));
 }
 
 // ------------------------------------------------------------------ host --
@@ -291,10 +527,33 @@ template <typename T>
 mclahe_status gauss_pass(const T *in, float *out, int64_t nvox, int64_t n, int64_t S, int r, const Weights &W,
                          hipStream_t st)
 {
-    if (S == 1) {
+    if (S == 1 && n <= kTile) {
+        // rows per work-group: about kTile outputs, at most 64 KiB of LDS
+        const int rpg = (int)std::max<int64_t>(1, std::min<int64_t>(kTile / n, 16384 / (n + 2 * r)));
+        const int64_t rows = nvox / n;
+        const int64_t blocks = (rows + rpg - 1) / rpg;
+        if (blocks > 0x7fffffff) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large for one pass");
+        const dim3 grid((uint32_t)blocks), blk(kT);
+        const size_t lds = sizeof(float) * rpg * (n + 2 * r);
+#define ROWS(RR) \
+    case RR: hipLaunchKernelGGL((k_gauss_rows<T, RR>), grid, blk, lds, st, in, out, nvox, (int)n, r, rpg, W); break;
+        switch (r) {
+            ROWS(1) ROWS(2) ROWS(3) ROWS(4) ROWS(5) ROWS(6) ROWS(7) ROWS(8)
+        default: hipLaunchKernelGGL((k_gauss_rows<T, 0>), grid, blk, lds, st, in, out, nvox, (int)n, r, rpg, W);
+        }
+#undef ROWS
+    } else if (S == 1) {
         const int64_t blocks = (nvox + kTile - 1) / kTile;
-        hipLaunchKernelGGL(k_gauss_last<T>, dim3((uint32_t)blocks), dim3(kT), sizeof(float) * (kTile + 2 * r), st,
-                           in, out, nvox, n, r, W);
+        if (n > (1 << 30)) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "last axis longer than 2^30");
+        const dim3 grid((uint32_t)blocks), blk(kT);
+        const size_t lds = sizeof(float) * (kTile + 2 * r);
+#define LAST(RR) \
+    case RR: hipLaunchKernelGGL((k_gauss_last<T, RR>), grid, blk, lds, st, in, out, nvox, n, r, W); break;
+        switch (r) {
+            LAST(1) LAST(2) LAST(3) LAST(4) LAST(5) LAST(6) LAST(7) LAST(8)
+        default: hipLaunchKernelGGL((k_gauss_last<T, 0>), grid, blk, lds, st, in, out, nvox, n, r, W);
+        }
+#undef LAST
     } else {
         const bool vec = S % 4 == 0 && ((uintptr_t)in % (4 * sizeof(T))) == 0 && ((uintptr_t)out % 16) == 0;
         const int V = vec ? 4 : 1;
@@ -331,18 +590,46 @@ mclahe_status gauss_pass(const T *in, float *out, int64_t nvox, int64_t n, int64
     return MCLAHE_SUCCESS;
 }
 
+template <typename T, int NP, typename IX>
+void median_launch_np(const void *in, void *out, const MedGeom &g, bool vec, hipStream_t st)
+{
+    const T *i = (const T *)in;
+    T *o = (T *)out;
+    const bool exact = g.N == NP;
+    if constexpr (NP <= 8) {
+        if (vec) {
+            const dim3 grid((uint32_t)((g.nvox / 4 + kT - 1) / kT));
+            if (exact) hipLaunchKernelGGL((k_median_interior<T, NP, 4, true, IX>), grid, dim3(kT), 0, st, i, o, g);
+            else hipLaunchKernelGGL((k_median_interior<T, NP, 4, false, IX>), grid, dim3(kT), 0, st, i, o, g);
+            goto border;
+        }
+    }
+    {
+        const dim3 grid((uint32_t)((g.nvox + kT - 1) / kT));
+        if (exact) hipLaunchKernelGGL((k_median_interior<T, NP, 1, true, IX>), grid, dim3(kT), 0, st, i, o, g);
+        else hipLaunchKernelGGL((k_median_interior<T, NP, 1, false, IX>), grid, dim3(kT), 0, st, i, o, g);
+    }
+border:
+    if (g.slab_pre[g.D] > 0)
+        hipLaunchKernelGGL((k_median_border<T, NP>), dim3((uint32_t)((g.slab_pre[g.D] + kT - 1) / kT)), dim3(kT), 0,
+                           st, i, o, g);
+}
+
 template <typename T>
 mclahe_status median_launch(const void *in, void *out, const MedGeom &g, hipStream_t st)
 {
-    const uint32_t blocks = (uint32_t)((g.nvox + kT - 1) / kT);
-    const T *i = (const T *)in;
-    T *o = (T *)out;
-    if (g.N <= 2) hipLaunchKernelGGL((k_median<T, 2>), dim3(blocks), dim3(kT), 0, st, i, o, g);
-    else if (g.N <= 4) hipLaunchKernelGGL((k_median<T, 4>), dim3(blocks), dim3(kT), 0, st, i, o, g);
-    else if (g.N <= 8) hipLaunchKernelGGL((k_median<T, 8>), dim3(blocks), dim3(kT), 0, st, i, o, g);
-    else if (g.N <= 16) hipLaunchKernelGGL((k_median<T, 16>), dim3(blocks), dim3(kT), 0, st, i, o, g);
-    else if (g.N <= 32) hipLaunchKernelGGL((k_median<T, 32>), dim3(blocks), dim3(kT), 0, st, i, o, g);
-    else hipLaunchKernelGGL((k_median<T, 64>), dim3(blocks), dim3(kT), 0, st, i, o, g);
+    const int last = g.D - 1;
+    const bool vec = g.N <= 8 && g.k[last] == 1 && g.shape[last] % 4 == 0 &&
+                     ((uintptr_t)in % (4 * sizeof(T))) == 0 && ((uintptr_t)out % (4 * sizeof(T))) == 0;
+    if (g.nvox >= (1LL << 31)) {
+        if (g.N <= 8) median_launch_np<T, 8, uint64_t>(in, out, g, vec, st);
+        else median_launch_np<T, 64, uint64_t>(in, out, g, false, st);
+    } else if (g.N <= 2) median_launch_np<T, 2, uint32_t>(in, out, g, vec, st);
+    else if (g.N <= 4) median_launch_np<T, 4, uint32_t>(in, out, g, vec, st);
+    else if (g.N <= 8) median_launch_np<T, 8, uint32_t>(in, out, g, vec, st);
+    else if (g.N <= 16) median_launch_np<T, 16, uint32_t>(in, out, g, false, st);
+    else if (g.N <= 32) median_launch_np<T, 32, uint32_t>(in, out, g, false, st);
+    else median_launch_np<T, 64, uint32_t>(in, out, g, false, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mc_fail(MCLAHE_ERROR_HIP, "median launch failed: %s", hipGetErrorString(e));
     return MCLAHE_SUCCESS;
@@ -455,11 +742,29 @@ mclahe_status mclahe_median(const void *d_in, mclahe_dtype dtype, int ndim, cons
         g.stride[i] = st;
         st *= shape[i];
     }
+    for (int i = 0; i < g.N; ++i) {   // window value i: last axis fastest
+        int q = i;
+        int64_t off = 0;
+        for (int a = ndim - 1; a >= 0; --a) {
+            const int o = g.lo[a] + q % g.k[a];
+            g.woff[i][a] = (int8_t)o;
+            off += o * g.stride[a];
+            q /= g.k[a];
+        }
+        g.off[i] = off;
+    }
     const size_t esz = dtype == MCLAHE_U8 ? 1 : dtype == MCLAHE_U16 ? 2 : 4;
     const char *ib = (const char *)d_in, *ob = (const char *)d_out;
     if (ib < ob + esz * nvox && ob < ib + esz * nvox)
         return mc_fail(MCLAHE_ERROR_INVALID_VALUE, "input and output must not overlap");
-    if ((nvox + kT - 1) / kT > 0x7fffffff) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large");
+    if ((nvox + kT - 1) / kT >= (1LL << 32)) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large");
+    g.slab_pre[0] = 0;
+    for (int i = 0; i < ndim; ++i) {
+        g.b0[i] = window[i] > 1 ? -g.lo[i] : 0;
+        g.b1[i] = window[i] > 1 ? g.lo[i] + window[i] - 1 : 0;
+        const int64_t cnt = std::min<int64_t>(g.b0[i] + g.b1[i], shape[i]);
+        g.slab_pre[i + 1] = g.slab_pre[i] + cnt * (nvox / shape[i]);
+    }
     hipStream_t hs = (hipStream_t)hip_stream;
     if (dtype == MCLAHE_U8) return median_launch<uint8_t>(d_in, d_out, g, hs);
     if (dtype == MCLAHE_U16) return median_launch<uint16_t>(d_in, d_out, g, hs);

@@ -65,6 +65,9 @@ GAUSS_CASES = [
     ((33, 70), (2.5, 3.1), np.float32),                # radii 10 and 12: direct taps
     ((12, 3000), (0.0, 0.0), np.uint16),               # nothing to smooth: conversion
     ((3, 4096 * 3 + 5), (1.9, 1.1), np.float32),       # several last-axis tiles, ragged
+    ((5000,), (2.5,), np.uint8),                       # long row, radius 10: flat tile, any radius
+    ((3000, 1), (0.0, 5.0), np.float32),               # rows of one sample, radius 20
+    ((7, 2048), (0.0, 0.9), np.float32),               # one row per work-group
 ]
 
 
@@ -122,6 +125,34 @@ def test_median_exact(shape, window, dt):
     rng = np.random.default_rng(sum(shape) + len(window))
     x = _data(rng, shape, dt)
     np.testing.assert_array_equal(gpu_median(x, window), DN.median(x, window), err_msg=f"{shape} {window}")
+
+
+@pytest.mark.timeout(300)
+def test_median_over_2e31_voxels_sampled():
+    """The microscopy window on a uint8 volume of 512x512x109x80 voxels (over
+    2^31: 64-bit coordinates), checked at sampled voxels, all borders
+    included, and as a whole against the 32-bit path on its first frames."""
+    import torch
+    shape = (512, 512, 109, 80)
+    g = torch.Generator(device="cpu").manual_seed(21)
+    x = torch.randint(0, 256, shape, dtype=torch.uint8, generator=g)
+    xt = x.cuda()
+    out = torch.empty_like(xt)
+    from paper_1906_11355_amd import _lib
+    _lib.median_ptr(xt.data_ptr(), _lib.U8, shape, (2, 2, 2, 1), out.data_ptr(),
+                    torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(22)
+    pts = np.stack([rng.integers(0, n, 20000) for n in shape], axis=1)
+    pts[:64, 0] = 0
+    pts[64:128, 1] = 0
+    pts[128:192, 2] = 0
+    pts[192:256] = [[0, 0, 0, 0], [511, 511, 108, 79]] * 32
+    xn = x.numpy()
+    got = out[tuple(torch.from_numpy(pts[:, a]).cuda() for a in range(4))].cpu().numpy()
+    np.testing.assert_array_equal(got, DN.median_at(xn, (2, 2, 2, 1), pts))
+    del out, xt
+    torch.cuda.empty_cache()
 
 
 def test_median_misaligned():
