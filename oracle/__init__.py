@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "libmclahe_oracle.so")
 
 U8, U16, F32 = 0, 1, 2
 GLOBAL, KERNEL = 0, 1
+EQUAL, REPEATED, INTEGER = 0, 1, 2      # redistribution variants
 _DT = {np.dtype(np.uint8): U8, np.dtype(np.uint16): U16, np.dtype(np.float32): F32}
 _NP = {U8: np.uint8, U16: np.uint16, F32: np.float32}
 
@@ -50,6 +51,8 @@ def _bind(lib):
         ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.mclahe_oracle_run.restype = ctypes.c_int
+    lib.mclahe_oracle_run_variant.argtypes = lib.mclahe_oracle_run.argtypes + [ctypes.c_int] * 3
+    lib.mclahe_oracle_run_variant.restype = ctypes.c_int
     return lib
 
 
@@ -91,8 +94,12 @@ def geometry(shape, kernel_size, lib=None):
 
 def run(x: np.ndarray, kernel_size, n_bins: int, clip_limit: float,
         mode: int = GLOBAL, user_range=None, out_dtype=np.float32,
-        want_f64: bool = False, lib=None):
-    """Run the oracle; returns a dict of hist, clipped, lut, range, out (+out_f64)."""
+        want_f64: bool = False, lib=None, redistribution: int = EQUAL, rounds: int = 1,
+        centre_half: bool = False):
+    """Run the oracle; returns a dict of hist, clipped, lut, range, out (+out_f64).
+
+    redistribution, rounds and centre_half select the comparison variants
+    stated in the C source (defaults: the paper's method)."""
     lib = _load(lib)
     x = np.ascontiguousarray(x)
     if x.dtype not in _DT:
@@ -112,11 +119,12 @@ def run(x: np.ndarray, kernel_size, n_bins: int, clip_limit: float,
         ur = np.asarray(user_range, dtype=np.float32)
     sh, shp = _i64(x.shape)
     ks, ksp = _i64(kernel_size)
-    rc = lib.mclahe_oracle_run(
+    rc = lib.mclahe_oracle_run_variant(
         D, shp, ksp, int(n_bins), ctypes.c_float(clip_limit), int(mode),
         None if ur is None else ur.ctypes.data, _DT[x.dtype], x.ctypes.data, od,
         out.ctypes.data, hist.ctypes.data, clipped.ctypes.data, lut.ctypes.data,
-        rng.ctypes.data, None if f64 is None else f64.ctypes.data)
+        rng.ctypes.data, None if f64 is None else f64.ctypes.data,
+        int(redistribution), int(rounds), int(bool(centre_half)))
     if rc == 1:
         raise ValueError("invalid arguments")
     if rc:

@@ -47,6 +47,18 @@
  *  - output is float in [0,1]; integer output is min(M, floor(y*M + 0.5))
  *    evaluated in single precision with M the dtype maximum.
  *
+ * Variants for comparison with other CLAHE codes (mclahe_oracle_run_variant;
+ * the defaults above are the paper's method):
+ *  - repeated redistribution: after the equal share, bins above the clip
+ *    level are clipped again and the new excess shared again, for at most
+ *    `rounds` rounds, stopping early once no bin exceeds the level.  Round r
+ *    works in integer units of 1/n^r count (the clip level becomes C*n^r);
+ *  - integer redistribution: counts stay integers; every bin gets
+ *    floor(E / n) and the remainder R = E mod n goes one count each to the
+ *    bins 0, s, 2s, ... (R of them), s = max(n / R, 1);
+ *  - kernel centres at k*b + b/2 (integer division) instead of k*b + (b-1)/2;
+ *    the two coincide for odd b.
+ *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
  */
 #include <math.h>
@@ -58,6 +70,7 @@
 
 enum { ORC_U8 = 0, ORC_U16 = 1, ORC_F32 = 2 };
 enum { ORC_GLOBAL = 0, ORC_KERNEL = 1 };
+enum { ORC_REDIST_EQUAL = 0, ORC_REDIST_REPEATED = 1, ORC_REDIST_INTEGER = 2 };
 
 /* Eq. 1 and Eq. 2: padding per axis and its split; number of kernels. */
 int mclahe_oracle_geometry(int ndim, const int64_t *shape, const int64_t *ksize,
@@ -117,17 +130,19 @@ static float load_value(const void *in, int dtype, int64_t i)
  * Kernels are numbered row-major over the padded kernel grid.
  * Returns 0 on success, 1 on invalid arguments, 2 on allocation failure.
  */
-int mclahe_oracle_run(int ndim, const int64_t *shape, const int64_t *ksize,
-                      int n_bins, float clip_limit, int mode,
-                      const float *user_range, int in_dtype, const void *in,
-                      int out_dtype, void *out, int64_t *hist, int64_t *clipped,
-                      float *lut, float *range, double *out_f64)
+int mclahe_oracle_run_variant(int ndim, const int64_t *shape, const int64_t *ksize,
+                              int n_bins, float clip_limit, int mode,
+                              const float *user_range, int in_dtype, const void *in,
+                              int out_dtype, void *out, int64_t *hist, int64_t *clipped,
+                              float *lut, float *range, double *out_f64,
+                              int redistribution, int rounds, int centre_half)
 {
     int64_t pad[ORC_MAX_DIM], pad0[ORC_MAX_DIM], pad1[ORC_MAX_DIM],
         nk[ORC_MAX_DIM];
     if (mclahe_oracle_geometry(ndim, shape, ksize, pad, pad0, pad1, nk)) return 1;
     if (n_bins < 2 || !(clip_limit >= 0.0f) || isinf(clip_limit)) return 1;
     if (user_range && (mode != ORC_GLOBAL || !(user_range[0] < user_range[1]))) return 1;
+    if (redistribution < ORC_REDIST_EQUAL || redistribution > ORC_REDIST_INTEGER || rounds < 1) return 1;
     const int D = ndim, n = n_bins;
 
     int64_t nvox = 1, npad = 1, nker = 1, K = 1;
@@ -216,13 +231,32 @@ int mclahe_oracle_run(int ndim, const int64_t *shape, const int64_t *ksize,
         khi[k] = hi;
 
         int64_t *h = h_all + k * n;
-        /* clip and redistribute the excess equally, in units of 1/n count */
-        int64_t E = 0;
-        for (int j = 0; j < n; ++j) if (h[j] > C) E += h[j] - C;
         int64_t cdf0 = 0, cdfn = 0, acc = 0;
         int64_t *H = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        if (redistribution == ORC_REDIST_INTEGER) {
+            /* integer counts: an equal integer share, the remainder spread */
+            int64_t E = 0;
+            for (int j = 0; j < n; ++j) if (h[j] > C) E += h[j] - C;
+            const int64_t q = E / n, R = E % n;
+            const int64_t s = R ? (n / R > 1 ? n / R : 1) : 1;
+            for (int j = 0; j < n; ++j)
+                H[j] = (h[j] < C ? h[j] : C) + q + ((R && j % s == 0 && j / s < R) ? 1 : 0);
+        } else {
+            /* clip and redistribute the excess equally, in units of 1/n count;
+             * repeated: again in units of 1/n^r while an excess remains */
+            const int nr = redistribution == ORC_REDIST_REPEATED ? rounds : 1;
+            int64_t Cr = C;
+            for (int j = 0; j < n; ++j) H[j] = h[j];
+            for (int r = 1; r <= nr; ++r) {
+                int64_t E = 0;
+                for (int j = 0; j < n; ++j) if (H[j] > Cr) E += H[j] - Cr;
+                if (r > 1 && E == 0) break;
+                for (int j = 0; j < n; ++j)
+                    H[j] = (int64_t)n * (H[j] < Cr ? H[j] : Cr) + E;
+                Cr *= n;
+            }
+        }
         for (int j = 0; j < n; ++j) {
-            H[j] = (int64_t)n * (h[j] < C ? h[j] : C) + E;
             acc += H[j];                       /* inclusive cdf */
             if (j == 0) cdf0 = acc;
             if (clipped) clipped[k * n + j] = H[j];
@@ -249,8 +283,9 @@ int mclahe_oracle_run(int ndim, const int64_t *shape, const int64_t *ksize,
         for (int i = D - 1; i >= 0; --i) { xc[i] = rem % shape[i]; rem /= shape[i]; }
         for (int i = 0; i < D; ++i) {
             /* padded position minus the first kernel centre, doubled so that
-             * it is an integer: m = 2*(x + p0) - (b - 1) */
-            int64_t m = 2 * (xc[i] + pad0[i]) - (ksize[i] - 1);
+             * it is an integer: m = 2*(x + p0) - (b - 1), or - 2*(b/2) with
+             * the centre at b/2 */
+            int64_t m = 2 * (xc[i] + pad0[i]) - (centre_half ? 2 * (ksize[i] / 2) : ksize[i] - 1);
             k0[i] = m / (2 * ksize[i]);
             w[i] = (double)(m - 2 * ksize[i] * k0[i]) / (double)(2 * ksize[i]);
         }
@@ -298,4 +333,16 @@ int mclahe_oracle_run(int ndim, const int64_t *shape, const int64_t *ksize,
     }
     free(padded); free(h_all); free(map); free(klo); free(khi);
     return 0;
+}
+
+/* The paper's method: equal redistribution once, centres at k*b + (b-1)/2. */
+int mclahe_oracle_run(int ndim, const int64_t *shape, const int64_t *ksize,
+                      int n_bins, float clip_limit, int mode,
+                      const float *user_range, int in_dtype, const void *in,
+                      int out_dtype, void *out, int64_t *hist, int64_t *clipped,
+                      float *lut, float *range, double *out_f64)
+{
+    return mclahe_oracle_run_variant(ndim, shape, ksize, n_bins, clip_limit, mode, user_range, in_dtype, in,
+                                     out_dtype, out, hist, clipped, lut, range, out_f64,
+                                     ORC_REDIST_EQUAL, 1, 0);
 }

@@ -48,8 +48,13 @@ def f32_bin(v, lo, hi, n: int) -> int:
 
 
 def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
-                 adaptive: bool = False, user_range=None):
-    """Returns dict(hist, lut (Fractions), out (Fractions), nk)."""
+                 adaptive: bool = False, user_range=None, repeated_rounds: int = 1,
+                 centre_half: bool = False):
+    """Returns dict(hist, clipped (Fractions, in counts), lut (Fractions), out (Fractions), nk).
+
+    repeated_rounds > 1: the equal sharing is repeated while some bin still
+    exceeds the clip level (each round a real share E/n of the new excess);
+    centre_half: kernel centres at b//2 instead of (b-1)/2."""
     x = np.asarray(x)
     xf = x.astype(np.float32)
     D = x.ndim
@@ -67,7 +72,7 @@ def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
     else:
         glo, ghi = xf.min(), xf.max()
 
-    hist, lut, rng = {}, {}, {}
+    hist, lut, rng, clipped = {}, {}, {}, {}
     for kidx in itertools.product(*[range(v) for v in nk]):
         sl = tuple(slice(k * bb, (k + 1) * bb) for k, bb in zip(kidx, b))
         block = padded[sl].ravel()
@@ -77,8 +82,13 @@ def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
         for v in block:
             h[f32_bin(v, lo, hi, n)] += 1
         hist[kidx] = h
-        excess = sum(max(c - C, 0) for c in h)
-        hp = [Fraction(min(c, C)) + Fraction(excess, n) for c in h]
+        hp = [Fraction(c) for c in h]
+        for r in range(repeated_rounds):
+            excess = sum(max(c - C, 0) for c in hp)
+            if r > 0 and excess == 0:
+                break
+            hp = [min(c, Fraction(C)) + Fraction(excess) / n for c in hp]
+        clipped[kidx] = hp
         cdf = list(itertools.accumulate(hp))
         if cdf[-1] == cdf[0]:
             lut[kidx] = [Fraction(j, n - 1) for j in range(n)]
@@ -90,7 +100,7 @@ def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
         lower, dist = [], []
         for j in range(D):
             q = Fraction(xi[j] + pads[j][1])          # padded position
-            half = Fraction(b[j] - 1, 2)              # centre offset in a kernel
+            half = Fraction(b[j] // 2) if centre_half else Fraction(b[j] - 1, 2)   # centre offset
             klo = math.floor((q - half) / b[j])        # kernel whose centre is below
             c0 = klo * b[j] + half
             c1 = (klo + 1) * b[j] + half
@@ -106,4 +116,4 @@ def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
             lo, hi = rng[kk]
             y += coef * lut[kk][f32_bin(v, lo, hi, n)]
         out[xi] = y
-    return dict(hist=hist, lut=lut, out=out, nk=nk, range=rng, C=C)
+    return dict(hist=hist, clipped=clipped, lut=lut, out=out, nk=nk, range=rng, C=C)

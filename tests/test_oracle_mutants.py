@@ -21,14 +21,14 @@ MUTANTS = {
     "eq1_sign": ("2 * b - 1 - ((s - 1) % b)", "2 * b - 1 + ((s - 1) % b)"),
     "eq2_split_swapped": ("pad0[i] = p / 2;", "pad0[i] = (p + 1) / 2;"),
     "reflect_not_symmetric": ("if (x < 0) x = -x - 1;", "if (x < 0) x = -x;"),
-    "excess_dropped": ("H[j] = (int64_t)n * (h[j] < C ? h[j] : C) + E;",
-                       "H[j] = (int64_t)n * (h[j] < C ? h[j] : C);"),
+    "excess_dropped": ("H[j] = (int64_t)n * (H[j] < Cr ? H[j] : Cr) + E;",
+                       "H[j] = (int64_t)n * (H[j] < Cr ? H[j] : Cr);"),
     "clip_ceil": ("(int64_t)floor((double)clip_limit * (double)K)",
                   "(int64_t)ceil((double)clip_limit * (double)K)"),
     "cdf_exclusive": ("acc += H[j];\n            double m", "double m"),
     "weights_swapped": ("coef *= bit ? w[i] : 1.0 - w[i];", "coef *= bit ? 1.0 - w[i] : w[i];"),
-    "centre_b_over_2": ("int64_t m = 2 * (xc[i] + pad0[i]) - (ksize[i] - 1);",
-                        "int64_t m = 2 * (xc[i] + pad0[i]) - 2 * (ksize[i] / 2);"),
+    "centre_b_over_2": ("(centre_half ? 2 * (ksize[i] / 2) : ksize[i] - 1)",
+                        "(centre_half ? 2 * (ksize[i] / 2) : 2 * (ksize[i] / 2))"),
     "bin_round_not_trunc": ("return (int)t;", "return (int)(t + 0.5f) < n ? (int)(t + 0.5f) : n - 1;"),
     "ahr_map_uses_global": ("float sc = mode == ORC_KERNEL ? (float)n / (hi - lo) : gscale;",
                             "float sc = gscale; lo = glo; hi = ghi;"),
