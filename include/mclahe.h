@@ -153,6 +153,37 @@ mclahe_status mclahe_plan_geometry(mclahe_plan_t plan, mclahe_geometry *geom);
 mclahe_status mclahe_plan_get_tuning(mclahe_plan_t plan, mclahe_tuning *tuning);
 mclahe_status mclahe_plan_set_tuning(mclahe_plan_t plan, const mclahe_tuning *tuning);
 
+/* Method variants for comparison with other CLAHE codes (a plan setting;
+ * the default is the paper's method as read above):
+ *   redistribution MCLAHE_REDIST_EQUAL    : the excess shared equally once;
+ *                  MCLAHE_REDIST_REPEATED : shared equally, then the bins
+ *                      above the clip level clipped again and the new excess
+ *                      shared again, at most `rounds` (1..8) rounds, stopping
+ *                      once no bin exceeds the level; round r counts in
+ *                      integer units of 1/n_bins^r (clipped array likewise,
+ *                      per kernel in the units of its last round); needs
+ *                      n_bins^rounds * K < 2^63 (else NOT_SUPPORTED);
+ *                  MCLAHE_REDIST_INTEGER  : integer counts: every bin gets
+ *                      floor(E / n_bins), and the remainder R = E mod n_bins
+ *                      one count each in bins 0, s, 2s, ... (R bins),
+ *                      s = max(n_bins / R, 1) (clipped array in counts);
+ *   centre MCLAHE_CENTRE_MIDDLE: kernel centres at k*b + (b-1)/2 (default);
+ *          MCLAHE_CENTRE_HALF  : at k*b + b/2 (integer division), the
+ *                                convention of some 2D codes (same for odd b).
+ * Setting a variant re-derives the plan; workspace sizes do not change.
+ * Errors: INVALID_VALUE for unknown values or rounds outside 1..8. */
+typedef enum {
+    MCLAHE_REDIST_EQUAL = 0, MCLAHE_REDIST_REPEATED = 1, MCLAHE_REDIST_INTEGER = 2
+} mclahe_redistribution;
+typedef enum { MCLAHE_CENTRE_MIDDLE = 0, MCLAHE_CENTRE_HALF = 1 } mclahe_centre;
+typedef struct {
+    int32_t redistribution;   /* mclahe_redistribution                      */
+    int32_t rounds;           /* repeated redistribution: most rounds (1..8) */
+    int32_t centre;           /* mclahe_centre                               */
+} mclahe_variant;
+mclahe_status mclahe_plan_get_variant(mclahe_plan_t plan, mclahe_variant *variant);
+mclahe_status mclahe_plan_set_variant(mclahe_plan_t plan, const mclahe_variant *variant);
+
 /* Workspace bytes for mclahe_run with the plan's current tuning.            */
 mclahe_status mclahe_workspace_size(mclahe_plan_t plan, size_t *bytes);
 

@@ -48,6 +48,14 @@ class Tuning(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Variant(ctypes.Structure):
+    _fields_ = [("redistribution", ctypes.c_int32), ("rounds", ctypes.c_int32), ("centre", ctypes.c_int32)]
+
+
+REDIST = {"equal": 0, "repeated": 1, "integer": 2}
+CENTRE = {"middle": 0, "half": 1}
+
+
 class MetricsResult(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 2), ("hi", ctypes.c_double * 2), ("mean", ctypes.c_double * 2),
                 ("std", ctypes.c_double * 2), ("entropy", ctypes.c_double * 2), ("mse", ctypes.c_double),
@@ -83,6 +91,8 @@ def _load():
         "mclahe_plan_geometry": [P, ctypes.POINTER(Geometry)],
         "mclahe_plan_get_tuning": [P, ctypes.POINTER(Tuning)],
         "mclahe_plan_set_tuning": [P, ctypes.POINTER(Tuning)],
+        "mclahe_plan_get_variant": [P, ctypes.POINTER(Variant)],
+        "mclahe_plan_set_variant": [P, ctypes.POINTER(Variant)],
         "mclahe_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_workspace_layout": [P, ctypes.POINTER(Layout)],
         "mclahe_run": [P, P, P, P, ctypes.c_size_t, P],
@@ -204,6 +214,18 @@ class Plan:
     def set_tuning(self, **kw):
         t = Tuning(**{k: int(v) for k, v in kw.items()})
         _check(lib.mclahe_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def set_variant(self, redistribution="equal", rounds: int = 1, centre="middle"):
+        """Comparison variants of the method (default: the paper's)."""
+        v = Variant(REDIST.get(redistribution, redistribution) if isinstance(redistribution, str) else int(redistribution),
+                    int(rounds),
+                    CENTRE.get(centre, centre) if isinstance(centre, str) else int(centre))
+        _check(lib.mclahe_plan_set_variant(self._h, ctypes.byref(v)))
+
+    def variant(self) -> dict:
+        v = Variant()
+        _check(lib.mclahe_plan_get_variant(self._h, ctypes.byref(v)))
+        return {"redistribution": v.redistribution, "rounds": v.rounds, "centre": v.centre}
 
     def workspace_size(self) -> int:
         n = ctypes.c_size_t()

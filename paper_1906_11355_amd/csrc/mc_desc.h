@@ -24,11 +24,14 @@
 
 enum { MC_U8 = 0, MC_U16 = 1, MC_F32 = 2 };
 enum { MC_GHR = 0, MC_AHR = 1 };
+enum { MC_REDIST_EQUAL = 0, MC_REDIST_REPEATED = 1, MC_REDIST_INTEGER = 2 };
 
 // One axis of the padded kernel grid: size s, kernel b, padding p0 before and
-// p1 after (Eq. 1-2), n = (s + p0 + p1) / b kernels.
+// p1 after (Eq. 1-2), n = (s + p0 + p1) / b kernels; cw = twice the offset of
+// a kernel's centre from its first sample: b - 1 (centre in the middle), or
+// 2 * (b / 2) for the comparison variant with the centre at b / 2.
 struct McAxis {
-    int32_t s, b, p0, p1, n;
+    int32_t s, b, p0, p1, n, cw;
 };
 
 // Original-coordinate footprint of kernel k along one axis: every padded
@@ -83,10 +86,11 @@ MC_HD void mc_cell_range(const McAxis &a, int32_t c, int32_t &lo, int32_t &hi)
 }
 
 // Doubled offset of x from the lower kernel centre of its cell c:
-// m = 2(x + p0) - (b - 1) - 2bc, in [0, 2b); weight = m / (2b).
+// m = 2(x + p0) - cw - 2bc, in [0, 2b); weight = m / (2b).  (Both centre
+// conventions give the same cells: the first voxel at or past a centre.)
 MC_HD int32_t mc_cell_m(const McAxis &a, int32_t c, int32_t x)
 {
-    return 2 * (x + a.p0) - (a.b - 1) - 2 * a.b * c;
+    return 2 * (x + a.p0) - a.cw - 2 * a.b * c;
 }
 
 // LDS stride (floats) of one bin's row in the staged GHR LUTs: nlk last-axis
@@ -119,6 +123,8 @@ struct McVol {
     float user_lo, user_hi;
     int64_t clipC;            // clip count C = floor(clip * K)
     int64_t K;                // voxels per kernel
+    int32_t redist, rounds;   // redistribution of the excess (MC_REDIST_*), and
+                              // the most rounds of the repeated variant
     McAxis ax[MC_MAXD];
     int64_t stride[MC_MAXD];  // element strides (C-contiguous)
     int64_t nvox, nker;

@@ -746,6 +746,58 @@ __device__ void hist_unit_dispatch(const McVol &d, uint32_t wu, char *smem)
 // ----------------------------------------------------- clip + CDF + LUT --
 // One unit per kernel: sum the partial histograms, clip at C and share the
 // excess equally (H = n*min(h,C) + E, exact), inclusive CDF, normalised LUT.
+// Comparison variants (d.redist): the equal sharing repeated while an excess
+// remains, at most d.rounds rounds, round r in units of 1/n^r (the clip level
+// becomes C n^r); or integer counts, floor(E/n) to every bin and the
+// remainder R one each to bins 0, s, 2s, .. (s = max(n/R, 1)).  Their H goes
+// through the clipped array, which each thread reads back for its own bins.
+__device__ __forceinline__ void clip_variant(const McVol &d, uint32_t k, const uint32_t *hk, int j0, int j1,
+                                          unsigned long long C, unsigned long long E, unsigned long long *s64)
+{
+    const int nb = d.nb;
+    const unsigned long long nbu = (unsigned long long)nb;
+    unsigned long long *Hk = d.clipped + (int64_t)k * nb;
+    unsigned long long tsum = 0;
+    if (d.redist == MC_REDIST_INTEGER) {
+        const unsigned long long q = E / nbu, R = E - q * nbu;
+        const unsigned long long st = R ? (nbu / R > 1 ? nbu / R : 1ull) : 1ull;
+        for (int j = j0; j < j1; ++j) {
+            const unsigned long long h = hk[j], ju = (unsigned long long)j;
+            const unsigned long long H = (h < C ? h : C) + q + ((R && ju % st == 0 && ju / st < R) ? 1ull : 0ull);
+            Hk[j] = H;
+            tsum += H;
+        }
+    } else {
+        for (int j = j0; j < j1; ++j) {
+            const unsigned long long h = hk[j];
+            Hk[j] = nbu * (h < C ? h : C) + E;
+        }
+        unsigned long long Cr = C * nbu;
+        for (int r = 2; r <= d.rounds; ++r) {
+            unsigned long long ex = 0;
+            for (int j = j0; j < j1; ++j) ex += Hk[j] > Cr ? Hk[j] - Cr : 0ull;
+            const unsigned long long Er = block_sum_u64(ex, s64);
+            if (Er == 0) break;                 // block-uniform
+            for (int j = j0; j < j1; ++j) Hk[j] = nbu * (Hk[j] < Cr ? Hk[j] : Cr) + Er;
+            Cr *= nbu;
+        }
+        for (int j = j0; j < j1; ++j) tsum += Hk[j];
+    }
+    const unsigned long long pre = block_exscan_u64(tsum, s64);
+    if (threadIdx.x == MC_T - 1) s64[0] = pre + tsum;
+    if (threadIdx.x == 0) s64[1] = Hk[0];       // bin 0 is thread 0's own
+    __syncthreads();
+    const unsigned long long total = s64[0], c0 = s64[1];
+    const unsigned long long den = total - c0;
+    unsigned long long acc = pre;
+    float *lk = d.lut + (int64_t)k * nb;
+    for (int j = j0; j < j1; ++j) {
+        acc += Hk[j];
+        const double m = den == 0 ? (double)j / (double)(nb - 1) : (double)(acc - c0) / (double)den;
+        lk[j] = (float)m;
+    }
+}
+
 __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
 {
     unsigned long long *s64 = (unsigned long long *)smem;
@@ -774,6 +826,10 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
     }
     const unsigned long long E = block_sum_u64(exc, s64);
     const unsigned long long nbu = (unsigned long long)nb;
+    if (d.redist != MC_REDIST_EQUAL) {
+        clip_variant(d, k, hk, j0, j1, C, E, s64);
+        return;
+    }
     const unsigned long long tsum = nbu * smin + (unsigned long long)(j1 - j0) * E;
     const unsigned long long pre = block_exscan_u64(tsum, s64);
     // c0 = H_0, total = sum H (= n*K); both block-uniform
@@ -969,8 +1025,8 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
         allv = allv && val[e];
         int c = cA;
         if (val[e]) {
-            // cell of x on the last axis: m = 2(x+p0) - (b-1), c = m / 2b
-            const int m = 2 * (x + al.p0) - (al.b - 1);
+            // cell of x on the last axis: m = 2(x+p0) - cw, c = m / 2b
+            const int m = 2 * (x + al.p0) - al.cw;
             c = m / (2 * al.b);
         }
         lbase[e] = (c - cA) * NO;

@@ -74,6 +74,7 @@ struct mclahe_plan_s {
     int64_t stride[MC_MAXD];
     int64_t nvox, nker, K, clipC, ncells;
     mclahe_tuning tune;  // requested (0 = default)
+    int redist = MC_REDIST_EQUAL, rounds = 1, centre_half = 0;   // method variant
     McVol v;             // derived descriptor (no pointers)
     // workspace layout
     uint64_t o_part, o_rpart, o_hist, o_clipped, o_lut, o_range, o_scale, total;
@@ -148,6 +149,8 @@ static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox)
     v.user_hi = p->ur[1];
     v.clipC = p->clipC;
     v.K = p->K;
+    v.redist = p->redist;
+    v.rounds = p->rounds;
     for (int i = 0; i < MC_MAXD; ++i) {
         v.ax[i] = p->ax[i];
         v.stride[i] = p->stride[i];
@@ -1176,6 +1179,7 @@ mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, c
         p->ax[i].p0 = (int32_t)(pad / 2);                // Eq. 2
         p->ax[i].p1 = (int32_t)((pad + 1) / 2);
         p->ax[i].n = (int32_t)((s + pad) / b);
+        p->ax[i].cw = (int32_t)(b - 1);                   // centre at k*b + (b-1)/2
         p->nvox *= s;
         p->nker *= p->ax[i].n;
         p->K *= b;
@@ -1186,7 +1190,7 @@ mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, c
         }
     }
     for (int i = ndim; i < MC_MAXD; ++i) {
-        p->ax[i] = McAxis{1, 1, 0, 1, 2};
+        p->ax[i] = McAxis{1, 1, 0, 1, 2, 0};
         p->shape[i] = p->ks[i] = 1;
     }
     if (p->K >= ((int64_t)1 << 32)) {
@@ -1274,6 +1278,36 @@ mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
         g_err = msg;
     }
     return s;
+}
+
+mclahe_status mclahe_plan_get_variant(mclahe_plan_t p, mclahe_variant *v)
+{
+    if (!p || !v) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    v->redistribution = p->redist;
+    v->rounds = p->rounds;
+    v->centre = p->centre_half;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_plan_set_variant(mclahe_plan_t p, const mclahe_variant *v)
+{
+    if (!p || !v) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    if (v->redistribution < MCLAHE_REDIST_EQUAL || v->redistribution > MCLAHE_REDIST_INTEGER)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "unknown redistribution %d", v->redistribution);
+    if (v->centre != MCLAHE_CENTRE_MIDDLE && v->centre != MCLAHE_CENTRE_HALF)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "unknown centre convention %d", v->centre);
+    const int rounds = v->redistribution == MCLAHE_REDIST_REPEATED ? v->rounds : 1;
+    if (rounds < 1 || rounds > 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "rounds must be in 1..8");
+    // the last round counts in units of 1/n^rounds: n^rounds * K must fit
+    long double units = (long double)p->K;
+    for (int r = 0; r < rounds; ++r) units *= (long double)p->nb;
+    if (units >= 9.0e18L)
+        return fail(MCLAHE_ERROR_NOT_SUPPORTED, "n_bins^rounds * kernel voxels must stay below 2^63");
+    p->redist = v->redistribution;
+    p->rounds = rounds;
+    p->centre_half = v->centre;
+    for (int i = 0; i < p->D; ++i) p->ax[i].cw = (int32_t)(v->centre ? 2 * (p->ks[i] / 2) : p->ks[i] - 1);
+    return derive(p);
 }
 
 mclahe_status mclahe_workspace_size(mclahe_plan_t p, size_t *bytes)

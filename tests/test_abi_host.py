@@ -419,3 +419,26 @@ def test_median_argument_checks(kw, status):
     with pytest.raises(MclaheError) as e:
         _lib.median_ptr(a["src"], a["code"], a["shape"], a["window"], a["dst"], 0)
     assert e.value.status == status
+
+
+# ---------------------------------------------------------------- variants --
+def test_variant_roundtrip_and_checks():
+    p = Plan((64, 64), (16, 16), 256, 0.02)
+    assert p.variant() == {"redistribution": 0, "rounds": 1, "centre": 0}
+    p.set_variant("repeated", 4, "half")
+    assert p.variant() == {"redistribution": 1, "rounds": 4, "centre": 1}
+    p.set_variant("integer", 7)                 # rounds only matter for "repeated"
+    assert p.variant() == {"redistribution": 2, "rounds": 1, "centre": 0}
+    ws = p.workspace_size()
+    p.set_variant("equal")
+    assert p.workspace_size() == ws
+    for bad in (dict(redistribution=3), dict(redistribution="repeated", rounds=0),
+                dict(redistribution="repeated", rounds=9), dict(centre=2)):
+        with pytest.raises(MclaheError) as e:
+            p.set_variant(**bad)
+        assert e.value.status == _lib.INVALID_VALUE
+    big = Plan((256, 256), (128, 128), 8192, 0.02)
+    with pytest.raises(MclaheError) as e:
+        big.set_variant("repeated", 5)          # 8192^5 * 16384 units overflow 64 bits
+    assert e.value.status == _lib.NOT_SUPPORTED
+    big.set_variant("repeated", 2)
