@@ -39,11 +39,17 @@ CLIP = 0.02
 PAPER_SIGMA = (0.7, 0.7, 0.9, 1.3)   # pre-smoothing of the photoemission run: momenta, energy, time
 
 
+# sources the contrast-metric and pre-denoising filters are built from; they
+# do not enter the MCLAHE kernels
+NON_MCLAHE_SOURCES = ("mc_metrics.hip", "mc_denoise.hip")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the MCLAHE kernels and their launches are built from."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_1906_11355_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
+        if f.endswith((".h", ".hip")) and f not in NON_MCLAHE_SOURCES:
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -76,6 +82,7 @@ def parse():
     ap.add_argument("--skip-serve", action="store_true", help="leave out the serving sweep")
     ap.add_argument("--skip-chunked", action="store_true", help="leave out the out-of-core run")
     ap.add_argument("--skip-denoise", action="store_true", help="leave out the pre-denoising filters")
+    ap.add_argument("--skip-variants", action="store_true", help="leave out the method-variant timings")
     ap.add_argument("--skip-metrics", action="store_true",
                     help="leave out the contrast-metric timing and the 3D-per-frame vs 4D table")
     ap.add_argument("--rates", default="10,30,100,300,1000,2000", help="serving arrival rates, req/s")
@@ -186,6 +193,9 @@ def main():
     if not args.skip_configs:
         res["configs"] = bench_configs(torch, np, _lib, synth, x, dev)
         log(f"configs: {res['configs']}")
+    if not args.skip_variants:
+        res["variants"] = bench_variants(torch, np, _lib, x, dev)
+        log(f"variants: {res['variants']}")
     if not args.skip_denoise:
         res["denoise"] = bench_denoise(torch, np, _lib, x, dev)
         log(f"denoise: {res['denoise']}")
@@ -354,6 +364,20 @@ def bench_metrics(torch, np, _lib, x, g_out, dev, steps=10):
     out["table_note"] = ("synthetic photoemission-like volume (not the paper's data), Gaussian-smoothed "
                          "with sigma (0.7, 0.7, 0.9, 1.3) before CLAHE; MSE against the min-max normalised "
                          "raw volume, PSNR with peak 2^23, STD and 256-bin entropy of each result")
+    return out
+
+
+def bench_variants(torch, np, _lib, x, dev, steps=10):
+    """The headline run under each comparison variant of the method (clip
+    step and centre convention): whole-step and per-pass times."""
+    out = {}
+    for name, var in (("paper", dict()), ("repeated_3_rounds", dict(redistribution="repeated", rounds=3)),
+                      ("integer", dict(redistribution="integer")), ("centre_half", dict(centre="half"))):
+        plan = _lib.Plan(SHAPE, KSIZE, NBINS, CLIP, "global", in_dtype="float32", out_dtype="float32")
+        if var:
+            plan.set_variant(**var)
+        ms, passes = time_plan(torch, _lib, plan, x, dev, steps)
+        out[name] = {"ms_per_step": round(ms, 4), "pass_ms": passes}
     return out
 
 
