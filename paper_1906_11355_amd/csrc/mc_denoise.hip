@@ -14,6 +14,8 @@
 //     sides, and every output reads its taps at fixed offsets;
 //   - longer rows: a flat tile of 2048 outputs plus r halo samples on each
 //     side (reflection never reaches further than r from an output);
+//   - the last two axes, both smoothed, rows of at most 512 samples: one
+//     fused pass through LDS (k_gauss_last2);
 //   - any other axis (stride S): a thread owns 4 (or 1) adjacent columns and
 //     sweeps a segment of the axis with a ring of 2r + 1 samples in
 //     registers, unrolled by the ring length so that every slot index is a
@@ -150,15 +152,25 @@ __global__ void __launch_bounds__(kT) k_gauss_rows(const T *in, float *out, int6
     const int cnt = (int)std::min<int64_t>((int64_t)rows_per_group * n, nvox - e0);
     const int dr = kT / n, dp = kT % n;
     {
+        // 8 loads per thread in flight before they are stored
         int row = threadIdx.x / n, p = threadIdx.x % n;
-        for (int i = threadIdx.x; i < cnt; i += kT) {
-            rowbuf[row * rs + r + p] = ld1(in, e0 + i);
-            row += dr;
-            p += dp;
-            if (p >= n) {
-                p -= n;
-                ++row;
+        for (int i0 = threadIdx.x; i0 < cnt; i0 += 8 * kT) {
+            float v[8];
+            int slot[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (i0 + k * kT < cnt) v[k] = ld1(in, e0 + i0 + k * kT);
+                slot[k] = row * rs + r + p;
+                row += dr;
+                p += dp;
+                if (p >= n) {
+                    p -= n;
+                    ++row;
+                }
             }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + k * kT < cnt) rowbuf[slot[k]] = v[k];
         }
     }
     __syncthreads();
@@ -191,6 +203,130 @@ __global__ void __launch_bounds__(kT) k_gauss_rows(const T *in, float *out, int6
             p -= n;
             ++row;
         }
+    }
+}
+
+// The last two axes in one pass (both smoothed, rows of at most kFuseRow
+// samples): a work-group takes T2 consecutive rows along axis D-2 of one
+// outer index, loads them with r2 halo rows on each side (reflected along
+// axis D-2) into LDS, filters along axis D-2 into a second LDS buffer laid
+// out with r3 halo slots per row, fills those by reflection along the last
+// axis and filters along it.  The same chains as two separate passes, so
+// the result is identical; one round trip through HBM less.
+constexpr int kFuseRow = 512;
+constexpr int kFuseRowTab = kTile / 2 + 2 * kRadiusMax;       // rows a group loads, at most
+constexpr size_t kFuseLds = 65536 - sizeof(int) * kFuseRowTab;  // dynamic LDS of a group
+
+template <typename T, int R2, int R3>
+__global__ void __launch_bounds__(kT) k_gauss_last2(const T *in, float *out, int n2, int n3, int r2, int r3,
+                                                   int T2, Weights W2, Weights W3)
+{
+    if constexpr (R2 > 0) r2 = R2;
+    if constexpr (R3 > 0) r3 = R3;
+    extern __shared__ float4 lds4[];                      // 16-byte aligned
+    float *lds = reinterpret_cast<float *>(lds4);
+    __shared__ int rowsrc[kFuseRowTab];   // offset of the source row of each loaded row
+    const int nseg = (n2 + T2 - 1) / T2;
+    const int64_t outer = blockIdx.x / nseg;
+    const int q0 = (int)(blockIdx.x - outer * nseg) * T2;
+    const int rows = min(T2, n2 - q0);            // output rows of this group
+    const int la = rows + 2 * r2;                 // loaded rows
+    const int rs = n3 + 2 * r3;
+    float *A = lds;                               // [la][n3]
+    float *B = lds + (size_t)(T2 + 2 * r2) * n3;  // [rows][n3 + 2 r3]
+    const T *src = in + outer * (int64_t)n2 * n3;
+    for (int t = threadIdx.x; t < la; t += kT) rowsrc[t] = tap_pos(q0 - r2 + t, n2, r2 < n2) * n3;
+    __syncthreads();
+    // (row, position) of element i = threadIdx.x + k kT, stepped without
+    // divisions
+    const int t00 = threadIdx.x / n3, p00 = threadIdx.x - t00 * n3;
+    const int dt = kT / n3, dp = kT - dt * n3;
+    const int total = la * n3;
+    if (sizeof(T) == 4 && (n3 & 3) == 0 && ((uintptr_t)src & 15) == 0) {
+        // 16-byte loads: element quads (row t, positions 4c .. 4c+3)
+        const int nq = n3 >> 2, tq = threadIdx.x / nq, cq = threadIdx.x - tq * nq;
+        const int dtq = kT / nq, dcq = kT - dtq * nq;
+        int t = tq, c = cq;
+        for (int j0 = threadIdx.x; j0 < total / 4; j0 += 4 * kT) {
+            float4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (j0 + k * kT < total / 4)
+                    v[k] = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(src) + rowsrc[t] + 4 * c);
+                t += dtq;
+                c += dcq;
+                if (c >= nq) { c -= nq; ++t; }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (j0 + k * kT < total / 4) reinterpret_cast<float4 *>(A)[j0 + k * kT] = v[k];
+        }
+    } else {
+        int t = t00, p = p00;
+        for (int i0 = threadIdx.x; i0 < total; i0 += 8 * kT) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                v[k] = 0.f;
+                if (i0 + k * kT < total) v[k] = ld1(src, rowsrc[t] + p);
+                t += dt;
+                p += dp;
+                if (p >= n3) { p -= n3; ++t; }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + k * kT < total) A[i0 + k * kT] = v[k];
+        }
+    }
+    __syncthreads();
+    float w2[R2 > 0 ? 2 * R2 + 1 : 1];
+    if constexpr (R2 > 0) {
+#pragma unroll
+        for (int j = 0; j <= 2 * R2; ++j) w2[j] = W2.w[j];
+    }
+    int t = t00, p = p00;
+    for (int i = threadIdx.x; i < rows * n3; i += kT) {
+        float acc = 0.f;
+        if constexpr (R2 > 0) {
+#pragma unroll
+            for (int j = 0; j <= 2 * R2; ++j) acc = __builtin_fmaf(w2[j], A[(t + j) * n3 + p], acc);
+        } else {
+            for (int j = 0; j <= 2 * r2; ++j) acc = __builtin_fmaf(W2.w[j], A[(t + j) * n3 + p], acc);
+        }
+        B[t * rs + r3 + p] = acc;
+        t += dt;
+        p += dp;
+        if (p >= n3) { p -= n3; ++t; }
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < rows * 2 * r3; h += kT) {
+        const int t = h / (2 * r3), sl = h - t * 2 * r3;
+        const int q = sl < r3 ? sl - r3 : n3 + (sl - r3);
+        B[t * rs + r3 + q] = B[t * rs + r3 + tap_pos(q, n3, r3 < n3)];
+    }
+    __syncthreads();
+    float w3[R3 > 0 ? 2 * R3 + 1 : 1];
+    if constexpr (R3 > 0) {
+#pragma unroll
+        for (int j = 0; j <= 2 * R3; ++j) w3[j] = W3.w[j];
+    }
+    const int64_t ob = outer * (int64_t)n2 * n3 + (int64_t)q0 * n3;
+    t = t00;
+    p = p00;
+    for (int i = threadIdx.x; i < rows * n3; i += kT) {
+        const float *src = B + t * rs + p;
+        float acc = 0.f;
+        if constexpr (R3 > 0) {
+#pragma unroll
+            for (int j = 0; j <= 2 * R3; ++j) acc = __builtin_fmaf(w3[j], src[j], acc);
+        } else {
+            for (int j = 0; j <= 2 * r3; ++j) acc = __builtin_fmaf(W3.w[j], src[j], acc);
+        }
+        out[ob + i] = acc;
+        t += dt;
+        p += dp;
+        if (p >= n3) { p -= n3; ++t; }
     }
 }
 
@@ -590,6 +726,38 @@ mclahe_status gauss_pass(const T *in, float *out, int64_t nvox, int64_t n, int64
     return MCLAHE_SUCCESS;
 }
 
+// Rows of T2 per work-group for the fused last-two-axes pass: about kTile
+// outputs, LDS within 64 KiB.
+int fuse_rows(int n2, int n3, int r2, int r3)
+{
+    // at most kTile / 2 rows: the row table of the kernel holds T2 + 2 r2
+    int T2 = std::max(1, std::min({n2, kTile / n3, kTile / 2}));
+    while (T2 > 1 && sizeof(float) * ((size_t)(T2 + 2 * r2) * n3 + (size_t)T2 * (n3 + 2 * r3)) > kFuseLds) --T2;
+    return T2;
+}
+
+template <typename T>
+mclahe_status gauss_last2(const T *in, float *out, int64_t nvox, int n2, int n3, int r2, int r3, const Weights &W2,
+                          const Weights &W3, hipStream_t st)
+{
+    const int T2 = fuse_rows(n2, n3, r2, r3);
+    const int64_t outer = nvox / ((int64_t)n2 * n3);
+    const int64_t blocks = outer * ((n2 + T2 - 1) / T2);
+    if (blocks > 0x7fffffff) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large for one pass");
+    const size_t lds = sizeof(float) * ((size_t)(T2 + 2 * r2) * n3 + (size_t)T2 * (n3 + 2 * r3));
+    const dim3 grid((uint32_t)blocks), blk(kT);
+    // common radii as constants; any other pair runs the generic loops
+    if (r2 == 3 && r3 == 3) hipLaunchKernelGGL((k_gauss_last2<T, 3, 3>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    else if (r2 == 4 && r3 == 5) hipLaunchKernelGGL((k_gauss_last2<T, 4, 5>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    else if (r2 == 3 && r3 == 4) hipLaunchKernelGGL((k_gauss_last2<T, 3, 4>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    else if (r2 == 4 && r3 == 4) hipLaunchKernelGGL((k_gauss_last2<T, 4, 4>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    else if (r2 == 5 && r3 == 5) hipLaunchKernelGGL((k_gauss_last2<T, 5, 5>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    else hipLaunchKernelGGL((k_gauss_last2<T, 0, 0>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mc_fail(MCLAHE_ERROR_HIP, "gaussian pass launch failed: %s", hipGetErrorString(e));
+    return MCLAHE_SUCCESS;
+}
+
 template <typename T, int NP, typename IX>
 void median_launch_np(const void *in, void *out, const MedGeom &g, bool vec, hipStream_t st)
 {
@@ -648,6 +816,7 @@ mclahe_status mclahe_gaussian_workspace_size(int ndim, const int64_t *shape, con
     if (!sigma || !bytes) return mc_fail(MCLAHE_ERROR_INVALID_VALUE, "sigma and bytes must not be NULL");
     int passes = 0;
     for (int i = 0; i < ndim; ++i) passes += sigma[i] > 0.0;
+    // (a fused last-two-axes pass needs no more: the bound stays one volume)
     *bytes = passes >= 2 ? ((sizeof(float) * nvox + 255) & ~size_t(255)) : 0;
     return MCLAHE_SUCCESS;
 }
@@ -691,22 +860,46 @@ mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim,
         const hipError_t e = hipGetLastError();
         return e == hipSuccess ? MCLAHE_SUCCESS : mc_fail(MCLAHE_ERROR_HIP, "launch failed: %s", hipGetErrorString(e));
     }
+    // launches: one per smoothed axis, except that the last two axes go in
+    // one fused pass when both are smoothed and the rows are short
+    bool fuse = P >= 2 && axes[P - 1] == ndim - 1 && axes[P - 2] == ndim - 2 && shape[ndim - 1] <= kFuseRow;
+    if (fuse) {   // one row group must fit the LDS budget
+        const int64_t n3 = shape[ndim - 1];
+        const int r2 = gauss_radius(sigma[ndim - 2], truncate), r3 = gauss_radius(sigma[ndim - 1], truncate);
+        fuse = sizeof(float) * ((1 + 2 * r2) * n3 + (n3 + 2 * r3)) <= kFuseLds &&
+               shape[ndim - 2] * n3 < (1LL << 31);       // row offsets in 32 bits
+    }
+    const int L = fuse ? P - 1 : P;
     float *tmp = (float *)d_workspace;
     const float *src = nullptr;
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < L; ++k) {
         const int a = axes[k];
-        int64_t S = 1;
-        for (int i = a + 1; i < ndim; ++i) S *= shape[i];
+        float *dst = ((L - 1 - k) % 2 == 0) ? d_out : tmp;   // the last launch lands in d_out
         Weights W;
         int r;
         gauss_weights(sigma[a], truncate, W, r);
-        float *dst = ((P - 1 - k) % 2 == 0) ? d_out : tmp;   // the last pass lands in d_out
-        if (k == 0) {
-            if (in_dtype == MCLAHE_U8) s = gauss_pass<uint8_t>((const uint8_t *)d_in, dst, nvox, shape[a], S, r, W, st);
-            else if (in_dtype == MCLAHE_U16) s = gauss_pass<uint16_t>((const uint16_t *)d_in, dst, nvox, shape[a], S, r, W, st);
-            else s = gauss_pass<float>((const float *)d_in, dst, nvox, shape[a], S, r, W, st);
+        if (fuse && k == L - 1) {
+            Weights W3;
+            int r3;
+            gauss_weights(sigma[ndim - 1], truncate, W3, r3);
+            const int n2 = (int)shape[ndim - 2], n3 = (int)shape[ndim - 1];
+            if (k == 0) {
+                if (in_dtype == MCLAHE_U8) s = gauss_last2<uint8_t>((const uint8_t *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st);
+                else if (in_dtype == MCLAHE_U16) s = gauss_last2<uint16_t>((const uint16_t *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st);
+                else s = gauss_last2<float>((const float *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st);
+            } else {
+                s = gauss_last2<float>(src, dst, nvox, n2, n3, r, r3, W, W3, st);
+            }
         } else {
-            s = gauss_pass<float>(src, dst, nvox, shape[a], S, r, W, st);
+            int64_t S = 1;
+            for (int i = a + 1; i < ndim; ++i) S *= shape[i];
+            if (k == 0) {
+                if (in_dtype == MCLAHE_U8) s = gauss_pass<uint8_t>((const uint8_t *)d_in, dst, nvox, shape[a], S, r, W, st);
+                else if (in_dtype == MCLAHE_U16) s = gauss_pass<uint16_t>((const uint16_t *)d_in, dst, nvox, shape[a], S, r, W, st);
+                else s = gauss_pass<float>((const float *)d_in, dst, nvox, shape[a], S, r, W, st);
+            } else {
+                s = gauss_pass<float>(src, dst, nvox, shape[a], S, r, W, st);
+            }
         }
         if (s) return s;
         src = dst;

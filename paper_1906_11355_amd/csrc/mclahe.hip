@@ -988,11 +988,20 @@ static mclahe_status stage_table(const std::vector<char> &img, void *dst, hipStr
     if (!sl.ev) HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
     if (sl.used) HIPCHK(hipEventSynchronize(sl.ev));
     if (sl.cap < img.size()) {
-        if (sl.host) HIPCHK(hipHostFree(sl.host));
-        sl.host = nullptr;
-        sl.cap = 0;
-        HIPCHK(hipHostMalloc((void **)&sl.host, img.size(), hipHostMallocDefault));
-        sl.cap = img.size();
+        // grow the whole ring at once (pinned allocations are slow): later
+        // calls of this size or smaller then never allocate
+        size_t cap = size_t(64) << 10;
+        while (cap < img.size()) cap <<= 1;
+        for (StageSlot &o : g_stage) {
+            if (o.cap >= cap) continue;
+            if (o.used) HIPCHK(hipEventSynchronize(o.ev));
+            if (o.host) HIPCHK(hipHostFree(o.host));
+            o.host = nullptr;
+            o.cap = 0;
+            o.used = false;
+            HIPCHK(hipHostMalloc((void **)&o.host, cap, hipHostMallocDefault));
+            o.cap = cap;
+        }
     }
     memcpy(sl.host, img.data(), img.size());
     HIPCHK(hipMemcpyAsync(dst, sl.host, img.size(), hipMemcpyHostToDevice, st));

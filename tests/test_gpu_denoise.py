@@ -68,6 +68,9 @@ GAUSS_CASES = [
     ((5000,), (2.5,), np.uint8),                       # long row, radius 10: flat tile, any radius
     ((3000, 1), (0.0, 5.0), np.float32),               # rows of one sample, radius 20
     ((7, 2048), (0.0, 0.9), np.float32),               # one row per work-group
+    ((20, 500), (16.0, 16.0), np.float32),             # radius 64: too wide to fuse the last two axes
+    ((3, 2, 512), (0.0, 1.4, 0.6), np.uint8),          # fused last two axes, longest fused rows, first pass
+    ((4, 9, 1), (0.8, 2.2, 3.0), np.float32),          # fused, rows of one sample, generic radii
 ]
 
 
