@@ -501,10 +501,12 @@ def bench_batched(torch, np, _lib, items, dev):
                                    [w.data_ptr() for w in ws_v], [w.numel() for w in ws_v], tbl.data_ptr(),
                                    tbl.numel(), st)
 
-    def timeit(f, k=10):
-        f()          # first sight: direct launches
-        f()          # second: graph capture (batched entry)
-        f()          # third: first replay of the new graph
+    def timeit(f, k=20, warm=20):
+        # the first call launches directly, the second captures the batch's
+        # graph, the next ones replay it; the first replays of a new graph
+        # and the clocks settle within about 20 calls: time the steady state
+        for _ in range(warm):
+            f()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(k):
