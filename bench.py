@@ -216,12 +216,21 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # whole steps of the oracle on the full volume until about 10 s of
+        # CPU time have passed (at most 8 steps)
+        mode = oracle.GLOBAL if args.mode == "global" else oracle.KERNEL
         t = time.perf_counter()
-        r = oracle.run(x, KSIZE, NBINS, CLIP, oracle.GLOBAL if args.mode == "global" else oracle.KERNEL)
-        dt = time.perf_counter() - t
-        res["cpu_baseline"] = {"value": round(V / dt / 1e9, 5), "unit": "Gvoxel/s", "cores": cores,
+        steps = 0
+        while True:
+            r = oracle.run(x, KSIZE, NBINS, CLIP, mode)
+            steps += 1
+            dt = time.perf_counter() - t
+            if dt >= 10.0 or steps >= 8:
+                break
+        res["cpu_baseline"] = {"value": round(V * steps / dt / 1e9, 5), "unit": "Gvoxel/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"the full {'x'.join(map(str, SHAPE))} volume, one step ({dt:.1f} s)"}
+                               "sample": f"the full {'x'.join(map(str, SHAPE))} volume, {steps} whole steps "
+                                         f"({dt:.1f} s)"}
         res["parity_vs_oracle"] = {"max_abs_out": float(np.abs(g_out.astype(np.float64) - r["out"]).max())}
     print(json.dumps(res), flush=True)
 
