@@ -708,6 +708,7 @@ mclahe_status gauss_pass(const T *in, float *out, int64_t nvox, int64_t n, int64
         const int64_t blocks = (c.vcols * c.nseg + kT - 1) / kT;
         if (blocks > 0x7fffffff) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large for one pass");
         const dim3 grid((uint32_t)blocks), blk(kT);
+        static_assert(kRingMax == 8, "the ring launches below cover radii 1..8");
 #define RING(RR)                                                                              \
     case RR:                                                                                  \
         if (vec) hipLaunchKernelGGL((k_gauss_ring<T, 4, RR>), grid, blk, 0, st, in, out, c, W); \
