@@ -112,6 +112,23 @@ def gen_4d(shape=(256, 256, 128, 32), seed=3, slab=16):
     return out
 
 
+def gen_fm4d_torch(shape=(512, 512, 109, 144), seed=6, device="cuda"):
+    """Fluorescence-like 3D+t uint8 volume (x, y, z, t), t the fastest axis,
+    generated on the device: a fluorescence-like 3D frame (gen_3d) as the
+    rate, brightening linearly over time by 0.8..1.2, shot noise per frame,
+    clipped to [0, 255].  Returns a torch tensor on `device`."""
+    import torch
+    X, Y, Z, T = shape
+    base = torch.from_numpy(gen_3d((X, Y, Z), seed)).to(device)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty(shape, dtype=torch.uint8, device=device)
+    for t in range(T):
+        lam = base * (0.8 + 0.4 * t / max(1, T - 1))
+        out[..., t] = torch.poisson(lam, generator=g).clamp_(0, 255).to(torch.uint8)
+    return out
+
+
 @dataclass
 class MixItem:
     kind: str                 # "2d" | "3d" | "4d"
