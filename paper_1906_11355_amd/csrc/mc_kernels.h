@@ -409,6 +409,11 @@ struct Memb {
     uint32_t extra[V];
 };
 
+// Only three kernels can hold x: the one holding its padded position
+// (x + p0) / b, kernel 0 if x is mirrored at the start (x < p0), and the
+// last kernel if x is mirrored at the end (x >= s - p1): p0 and p1 are below
+// b, so each fold lies inside one kernel.  They are visited in ascending
+// order, as a scan of every kernel of the segment would find them.
 template <int V>
 __device__ __forceinline__ void build_memb(const McVol &d, int kA, int kB, int xs, int xe,
                                            int x0, Memb<V> &m)
@@ -421,8 +426,15 @@ __device__ __forceinline__ void build_memb(const McVol &d, int kA, int kB, int x
         m.w1[e] = 0;
         m.extra[e] = 0;
         if (x < xs || x >= xe) continue;
+        const int kd = (x + a.p0) / a.b;
+        int cand[3] = {x < a.p0 ? 0 : -1, kd, x >= a.s - a.p1 ? a.n - 1 : -1};
+        if (cand[0] == kd) cand[0] = -1;          // the same kernel counts once
+        if (cand[2] == kd) cand[2] = -1;
         int found = 0;
-        for (int k = kA; k < kB; ++k) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int k = cand[c];
+            if (k < kA || k >= kB) continue;
             const int w = mc_mult(mc_kernel_box(a, k), x);
             if (!w) continue;
             if (found == 0) {
