@@ -845,6 +845,7 @@ struct mclahe_timer_s {
 struct BatchLaunch {
     int phase;
     KFnB fn;
+    KFnB group;                   // clip pass: the volumes' histogram class
     int threads;
     size_t lds;
     std::vector<uint32_t> vols;   // volume indices
@@ -876,11 +877,19 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout
             if (!units) continue;
             size_t lds = 0;
             const KPair k = phase_kernels(p, p->v, ph, lds);
+            // the clip pass has one kernel for every volume; it is split by
+            // the volumes' histogram class so that each class forms a chain
+            // of launches that does not wait for the others (graph replay)
+            KFnB group = nullptr;
+            if (ph == 2) {
+                size_t lh = 0;
+                group = phase_kernels(p, p->v, 1, lh).batch;
+            }
             BatchLaunch *bl = nullptr;
             for (size_t j = first; j < L.launches.size(); ++j)
-                if (L.launches[j].fn == k.batch) bl = &L.launches[j];
+                if (L.launches[j].fn == k.batch && L.launches[j].group == group) bl = &L.launches[j];
             if (!bl) {
-                L.launches.push_back(BatchLaunch{ph, k.batch, k.threads, 0, {}, {0}});
+                L.launches.push_back(BatchLaunch{ph, k.batch, group, k.threads, 0, {}, {0}});
                 bl = &L.launches.back();
             }
             bl->lds = std::max(bl->lds, lds);
@@ -1010,23 +1019,26 @@ static mclahe_status stage_table(const std::vector<char> &img, void *dst, hipStr
     return MCLAHE_SUCCESS;
 }
 
-// Graph: the launches of one pass are independent branches; every launch of
-// pass ph depends on every launch of the previous non-empty pass.
+// Graph: a launch depends on the launches that last ran one of its volumes
+// (each volume's passes run in order; volumes share no workspace or output),
+// so the chains of different kernel classes overlap.
 static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std::vector<char> &img, char *table)
 {
     HIPCHK(hipGraphCreate(&g->graph, 0));
     const McLaunchRec *recs = (const McLaunchRec *)(img.data() + L.o_recs);
     const uint32_t *idx_dev = (const uint32_t *)(table + L.o_idx);
     const McVol *vols_dev = (const McVol *)(table + L.o_vols);
-    std::vector<hipGraphNode_t> prev, cur;
-    int cur_phase = -1;
+    std::vector<hipGraphNode_t> nodes(L.launches.size());
+    std::vector<int> last(L.view.size(), -1);   // latest launch of each volume
     for (size_t j = 0; j < L.launches.size(); ++j) {
         const BatchLaunch &bl = L.launches[j];
-        if (bl.phase != cur_phase) {
-            if (!cur.empty()) prev = cur;
-            cur.clear();
-            cur_phase = bl.phase;
-        }
+        std::vector<int> dep;
+        for (uint32_t v : bl.vols)
+            if (last[v] >= 0) dep.push_back(last[v]);
+        std::sort(dep.begin(), dep.end());
+        dep.erase(std::unique(dep.begin(), dep.end()), dep.end());
+        std::vector<hipGraphNode_t> prev;
+        for (int q : dep) prev.push_back(nodes[q]);
         if (bl.lds > 64 * 1024)
             HIPCHK(hipFuncSetAttribute((const void *)bl.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)bl.lds));
@@ -1045,7 +1057,8 @@ static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std:
         kp.kernelParams = args;
         hipGraphNode_t node;
         HIPCHK(hipGraphAddKernelNode(&node, g->graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
-        cur.push_back(node);
+        nodes[j] = node;
+        for (uint32_t v : bl.vols) last[v] = (int)j;
     }
     HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     return MCLAHE_SUCCESS;
@@ -1518,9 +1531,11 @@ static mclahe_status batched_launch(const BatchLayout &L, const std::vector<char
     for (size_t j = 0; j < L.launches.size(); ++j) {
         const BatchLaunch &bl = L.launches[j];
         char buf[96];
-        snprintf(buf, sizeof buf, ":%zx/%u/%u/%d/%zu", (size_t)(uintptr_t)bl.fn, recs[j].n, recs[j].units,
+        snprintf(buf, sizeof buf, ":%zx/%u/%u/%d/%zu/", (size_t)(uintptr_t)bl.fn, recs[j].n, recs[j].units,
                  bl.threads, bl.lds);
         key += buf;
+        // the graph's edges follow which volumes each launch runs
+        for (uint32_t v : bl.vols) key += std::to_string(v) + ",";
     }
     std::lock_guard<std::mutex> lk(g_graph_mu);
     ++g_tick;
