@@ -72,5 +72,42 @@ def build(jobs: int | None = None, csrc: str = CSRC, build_dir: str = BUILD, lib
     return lib
 
 
+def build_host_asan(build_dir: str, jobs: int | None = None) -> tuple[str, str]:
+    """A build of the same sources whose HOST code carries AddressSanitizer.
+
+    Device code is compiled as usual (at -O1) and never instrumented: the
+    sanitizer is passed to the host pass only.  Returns (library, runtime),
+    where runtime is the sanitizer's shared runtime, which a process must
+    preload before it loads the library.  For host-side checks on a machine
+    without a GPU (plan validation, geometry, workspace layout, batched tables,
+    tuning files).
+    """
+    os.makedirs(build_dir, exist_ok=True)
+    flags = [f for f in FLAGS if f != "-O3"] + [
+        "-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+    def one(src):
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+        r = subprocess.run([HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"compile failed: {src}")
+        return obj
+
+    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(one, SOURCES))
+    lib = os.path.join(build_dir, "libmclahe_asan.so")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host",
+                           "-fsanitize=address", *objs, "-o", lib + ".tmp"])
+    os.replace(lib + ".tmp", lib)
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    rt = subprocess.check_output([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
+    return lib, rt
+
+
 if __name__ == "__main__":
     print(build())
