@@ -121,6 +121,28 @@ def test_unaligned_pointers_and_rows():
     _case(z, (9, 16), 256, 0.03, in_offset=1, out_offset=4)
 
 
+@pytest.mark.parametrize("dtype,in_offset", [(np.float32, 0), (np.float32, 4), (np.uint16, 0), (np.uint8, 0),
+                                             (np.uint8, 3)])
+def test_global_range_many_units_ragged_tiles(dtype, in_offset):
+    """The global range pass at a size that gives it many units, a partial last
+    tile of vectors and a scalar tail: the minimum sits in the partial tile,
+    the maximum in the very last voxel, and each occurs once."""
+    shape = (1031, 2053)                      # 2,116,643 voxels, odd
+    rng = np.random.default_rng(41)
+    if dtype == np.float32:
+        x = rng.normal(50.0, 8.0, size=shape).clip(1.0, 99.0).astype(np.float32)
+        lo, hi = np.float32(-3.5), np.float32(250.25)
+    else:
+        top = 255 if dtype == np.uint8 else 65535
+        x = rng.integers(1, top, size=shape).astype(dtype)
+        lo, hi = dtype(0), dtype(top)
+    flat = x.reshape(-1)
+    flat[-1] = hi
+    flat[-20] = lo                            # after the last whole tile, for 1-, 4- and 8-voxel vectors
+    g, r = _case(x, (128, 256), 256, 0.02, "global", in_offset=in_offset)
+    assert g["range"].tolist() == [float(lo), float(hi)]
+
+
 def test_in_place():
     rng = np.random.default_rng(6)
     x = rng.poisson(5.0, size=(30, 40, 20)).astype(np.float32)
