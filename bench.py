@@ -109,8 +109,8 @@ def gen_mix_items(synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed "
-                                   "(see DESIGN.md) but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; sharding over several GPUs is "
+                                   "designed but not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
