@@ -102,11 +102,15 @@ def build_host_asan(build_dir: str, jobs: int | None = None) -> tuple[str, str]:
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host",
                            "-fsanitize=address", *objs, "-o", lib + ".tmp"])
     os.replace(lib + ".tmp", lib)
+    return lib, asan_runtime()
+
+
+def asan_runtime() -> str:
+    """Path of the AddressSanitizer shared runtime of hipcc's clang."""
     clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin", "clang")
     if not os.path.exists(clang):
         clang = "/opt/rocm/llvm/bin/clang"
-    rt = subprocess.check_output([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
-    return lib, rt
+    return subprocess.check_output([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
 
 
 if __name__ == "__main__":

@@ -40,9 +40,7 @@ def asan_lib():
     d = os.path.join(tempfile.gettempdir(), f"mclahe_host_asan_{_source_hash()}")
     lib = os.path.join(d, "libmclahe_asan.so")
     if os.path.exists(lib):
-        clang = "/opt/rocm/llvm/bin/clang"
-        rt = subprocess.check_output([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
-        return lib, rt
+        return lib, libbuild.asan_runtime()
     return libbuild.build_host_asan(d)
 
 
