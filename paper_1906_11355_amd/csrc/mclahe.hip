@@ -93,6 +93,8 @@ struct mclahe_plan_s {
 // Batched launches fill the chip with the units of many volumes, so they take
 // coarser units.
 static const int64_t kUnitVoxPlain = 16384, kUnitVoxBatch = 65536;
+// unit columns the plain interpolation pass keeps at least (one per CU)
+static const int64_t kMinMapCols = 256;
 
 static size_t esize(int dt) { return dt == MC_U8 ? 1 : dt == MC_U16 ? 2 : 4; }
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
@@ -134,7 +136,7 @@ static int seg_chunks(int xs, int xe, int V) { return (xe + V - 1) / V - xs / V;
 
 // Derive the work decomposition and workspace layout from the tuning, with
 // default work units of at least unit_vox voxels.
-static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox)
+static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox, int64_t min_map_cols)
 {
     McVol &v = p->v;
     memset(&v, 0, sizeof v);
@@ -269,12 +271,19 @@ static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox)
     const bool fast = D <= 4 && otab + map_lut_bytes(p, 1) <= MC_LDS_BUDGET;
     v.path = fast ? 0 : 1;
     const int ncl = al.n - 1;  // cells on the last axis
+    int64_t ocols = 1;         // interpolation cells on the outer axes
+    for (int i = 0; i < D - 1; ++i) ocols *= p->ax[i].n - 1;
     int mG = 1;
     if (fast && p->mode == MC_GHR) {
-        int want = t.map_group > 0 ? t.map_group : ncl;   // default: largest that fits
+        // default: the largest group that fits, but small enough that the
+        // volume has min_map_cols unit columns before any row split (a small
+        // volume in few wide units leaves most of the chip idle: 2D 512x512
+        // uint8, 8 cells per axis, groups of 8 -> 1: 40 -> 35 us per step)
+        int want = t.map_group > 0 ? t.map_group : ncl;
         want = std::min(want, ncl);
         for (int g = want; g >= 1; --g) {
             if (otab + map_lut_bytes(p, g) > MC_LDS_BUDGET) continue;
+            if (g > 1 && t.map_group <= 0 && ocols * ((ncl + g - 1) / g) < min_map_cols) continue;
             bool ok = true;
             for (int cA = 0; cA < ncl && ok; cA += g) {
                 int xs, xe, tmp;
@@ -399,7 +408,7 @@ static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox)
 // Both decompositions: the batched one (kept in p->bd), then the plain one.
 static mclahe_status derive(mclahe_plan_s *p)
 {
-    mclahe_status s = derive_core(p, kUnitVoxBatch);
+    mclahe_status s = derive_core(p, kUnitVoxBatch, 1);
     if (s) return s;
     p->bd.v = p->v;
     p->bd.o_part = p->o_part;
@@ -414,7 +423,7 @@ static mclahe_status derive(mclahe_plan_s *p)
     p->bd.lds_hist = p->lds_hist;
     p->bd.lds_clip = p->lds_clip;
     p->bd.lds_map = p->lds_map;
-    return derive_core(p, kUnitVoxPlain);
+    return derive_core(p, kUnitVoxPlain, kMinMapCols);
 }
 
 // A copy of the plan that carries the batched decomposition, for the
