@@ -442,3 +442,24 @@ def test_variant_roundtrip_and_checks():
         big.set_variant("repeated", 5)          # 8192^5 * 16384 units overflow 64 bits
     assert e.value.status == _lib.NOT_SUPPORTED
     big.set_variant("repeated", 2)
+
+
+def test_default_interpolation_groups_keep_256_unit_columns():
+    """Under a global range the default interpolation group is the largest that
+    fits the LDS while the volume keeps 256 unit columns (outer cells times
+    last-axis groups); an explicit group is taken as given."""
+    cases = [((512, 512), (64, 64), 256, 1),             # 8 x 8 cells: 8 columns per group of 1
+             ((1024, 1024), (64, 64), 256, 1),           # 16 x 16 cells: 256 columns only with groups of 1
+             ((256, 256, 128), (32, 32, 16), 256, 2),    # 64 outer cells x 4 groups of 2
+             ((128, 128, 64), (16, 16, 8), 256, 2),
+             ((256, 256, 128, 32), (32, 32, 16, 8), 512, 2)]   # LDS allows 2; 512 outer cells
+    for shape, ks, nb, want in cases:
+        p = Plan(shape, ks, nb, 0.02, "global")
+        assert p.tuning()["map_group"] == want, (shape, p.tuning())
+    p = Plan((512, 512), (64, 64), 256, 0.02, "global")
+    t = p.tuning()
+    t["map_group"] = 4
+    p.set_tuning(**t)
+    assert p.tuning()["map_group"] == 4
+    # per-kernel ranges interpolate one cell at a time
+    assert Plan((256, 256, 128), (32, 32, 16), 256, 0.02, "kernel").tuning()["map_group"] == 1
