@@ -478,7 +478,7 @@ def bench_variants(torch, np, _lib, x, dev, steps=10):
         plan = _lib.Plan(SHAPE, KSIZE, NBINS, CLIP, "global", in_dtype="float32", out_dtype="float32")
         if var:
             plan.set_variant(**var)
-        ms, passes = time_plan(torch, _lib, plan, x, dev, steps)
+        ms, passes, _ = time_plan(torch, _lib, plan, x, dev, steps)
         out[name] = {"ms_per_step": round(ms, 4), "pass_ms": passes}
     return out
 
@@ -548,7 +548,14 @@ def time_plan(torch, _lib, plan, x, dev, steps):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     p = timer.read()
-    return ms, {k: round(p[k], 4) for k in ("range", "hist", "clip", "map")}
+    # the same runs back to back, without events between the passes
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run_ptr(*ptrs)
+    torch.cuda.synchronize()
+    ms_b2b = (time.perf_counter() - t0) / steps * 1e3
+    return ms, {k: round(p[k], 4) for k in ("range", "hist", "clip", "map")}, ms_b2b
 
 
 def bench_configs(torch, np, _lib, synth, x4, dev):
@@ -564,10 +571,11 @@ def bench_configs(torch, np, _lib, synth, x4, dev):
     ]
     for name, x, ks, nb, clip, mode, steps in cases:
         plan = _lib.Plan(x.shape, ks, nb, clip, mode, in_dtype=str(x.dtype), out_dtype="float32")
-        ms, passes = time_plan(torch, _lib, plan, x, dev, steps)
+        ms, passes, ms_b2b = time_plan(torch, _lib, plan, x, dev, steps)
         V = x.size
         S = x.dtype.itemsize
         out[name] = {"ms_per_step": round(ms, 4), "us_per_step": round(ms * 1e3, 1),
+                     "us_per_step_back_to_back": round(ms_b2b * 1e3, 1),
                      "Gvoxel_s": round(V / ms / 1e6, 2), "pass_ms": passes,
                      "path_frac_of_hbm": round(V * (3 * S + 4) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     return out
