@@ -26,7 +26,10 @@
  *     (for hi == lo, scale is +inf and this gives v > lo ? n_bins-1 : 0);
  *   - global range = min and max of the input, unless the caller gives one;
  *     adaptive range = min and max over the kernel's padded voxels;
- *   - clip count C = floor((double)clip_limit * K), K = prod(kernel_size);
+ *   - clip count C = floor(clip_limit * K), K = prod(kernel_size), for the
+ *     decimal the caller wrote: a double product that falls short of the next
+ *     integer by at most 2^-40 of itself counts as that integer (0.02 with
+ *     K = 270000 gives 5400); C is capped at K (nothing is clipped there);
  *     excess E = sum_j max(h_j - C, 0) shared equally by all bins once; the
  *     library keeps it exact in units of 1/n_bins count:
  *       H_j = n_bins * min(h_j, C) + E;
@@ -130,14 +133,15 @@ typedef struct {
  *   shape        : ndim sizes s_i >= 1 (total voxels < 2^40)
  *   kernel_size  : ndim sizes 1 <= b_i <= s_i; prod(b) < 2^32
  *   n_bins       : 2..8192
- *   clip_limit   : finite, >= 0 (>= 1 disables clipping, 0 = uniform)
+ *   clip_limit   : finite, >= 0 (>= 1 disables clipping, 0 = uniform); a
+ *                  double, so that a decimal limit keeps its exact count
  *   mode         : MCLAHE_RANGE_GLOBAL or MCLAHE_RANGE_KERNEL
  *   user_range   : NULL, or {lo, hi} finite with lo < hi (GLOBAL only)
  *   in_dtype     : u8, u16 or f32 (f32 input must be finite)
  *   out_dtype    : f32 (values in [0,1]) or u8/u16 codes
  * Returns INVALID_VALUE for arguments outside these ranges.                 */
 mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape,
-                          const int64_t *kernel_size, int n_bins, float clip_limit,
+                          const int64_t *kernel_size, int n_bins, double clip_limit,
                           mclahe_range_mode mode, const float *user_range,
                           mclahe_dtype in_dtype, mclahe_dtype out_dtype);
 

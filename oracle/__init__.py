@@ -47,7 +47,7 @@ def _bind(lib):
     lib.mclahe_oracle_geometry.argtypes = [ctypes.c_int, i64p, i64p, i64p, i64p, i64p, i64p]
     lib.mclahe_oracle_geometry.restype = ctypes.c_int
     lib.mclahe_oracle_run.argtypes = [
-        ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_float, ctypes.c_int,
+        ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_double, ctypes.c_int,
         ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.mclahe_oracle_run.restype = ctypes.c_int
@@ -120,7 +120,7 @@ def run(x: np.ndarray, kernel_size, n_bins: int, clip_limit: float,
     sh, shp = _i64(x.shape)
     ks, ksp = _i64(kernel_size)
     rc = lib.mclahe_oracle_run_variant(
-        D, shp, ksp, int(n_bins), ctypes.c_float(clip_limit), int(mode),
+        D, shp, ksp, int(n_bins), ctypes.c_double(clip_limit), int(mode),
         None if ur is None else ur.ctypes.data, _DT[x.dtype], x.ctypes.data, od,
         out.ctypes.data, hist.ctypes.data, clipped.ctypes.data, lut.ctypes.data,
         rng.ctypes.data, None if f64 is None else f64.ctypes.data,

@@ -31,7 +31,11 @@
  *        scale = (float)n / (hi - lo);  t = (v - lo) * scale;
  *        bin = t > 0 ? (t >= n ? n-1 : (int)t) : 0,  and if hi == lo:
  *        bin = v > lo ? n-1 : 0;
- *  - clip_limit is a fraction of the kernel's voxel count K: C = floor(clip*K);
+ *  - clip_limit is a fraction of the kernel's voxel count K: C = floor(clip*K),
+ *    taken for the decimal the caller wrote: a double product that falls
+ *    short of the next integer by no more than 2^-40 of itself is that
+ *    integer (0.02 * 270000 -> 5400, 0.29 * 100 -> 29); C >= K clips nothing
+ *    and is reported as K;
  *    the excess E = sum max(h-C, 0) is shared equally by all n bins, once.  In
  *    units of 1/n count that is exactly H_j = n*min(h_j, C) + E;
  *  - the CDF is inclusive; map_j = (cdf_j - cdf_0) / (cdf_{n-1} - cdf_0),
@@ -71,6 +75,19 @@
 enum { ORC_U8 = 0, ORC_U16 = 1, ORC_F32 = 2 };
 enum { ORC_GLOBAL = 0, ORC_KERNEL = 1 };
 enum { ORC_REDIST_EQUAL = 0, ORC_REDIST_REPEATED = 1, ORC_REDIST_INTEGER = 2 };
+
+/* Clip count of Algorithm 1's clip step: the clip limit is a fraction of the
+ * kernel's K voxels.  The limit arrives as the binary double nearest the
+ * decimal the caller wrote, so clip*K may land a rounding error below the
+ * intended whole count; such a product is raised to that count. */
+static int64_t oracle_clip_count(double clip_limit, int64_t K)
+{
+    const double c = clip_limit * (double)K;
+    if (c >= (double)K) return K;                  /* no bin can exceed it */
+    int64_t C = (int64_t)floor(c);
+    if ((double)(C + 1) - c <= ldexp(c, -40)) C += 1;
+    return C;
+}
 
 /* Eq. 1 and Eq. 2: padding per axis and its split; number of kernels. */
 int mclahe_oracle_geometry(int ndim, const int64_t *shape, const int64_t *ksize,
@@ -131,7 +148,7 @@ static float load_value(const void *in, int dtype, int64_t i)
  * Returns 0 on success, 1 on invalid arguments, 2 on allocation failure.
  */
 int mclahe_oracle_run_variant(int ndim, const int64_t *shape, const int64_t *ksize,
-                              int n_bins, float clip_limit, int mode,
+                              int n_bins, double clip_limit, int mode,
                               const float *user_range, int in_dtype, const void *in,
                               int out_dtype, void *out, int64_t *hist, int64_t *clipped,
                               float *lut, float *range, double *out_f64,
@@ -140,7 +157,7 @@ int mclahe_oracle_run_variant(int ndim, const int64_t *shape, const int64_t *ksi
     int64_t pad[ORC_MAX_DIM], pad0[ORC_MAX_DIM], pad1[ORC_MAX_DIM],
         nk[ORC_MAX_DIM];
     if (mclahe_oracle_geometry(ndim, shape, ksize, pad, pad0, pad1, nk)) return 1;
-    if (n_bins < 2 || !(clip_limit >= 0.0f) || isinf(clip_limit)) return 1;
+    if (n_bins < 2 || !(clip_limit >= 0.0) || isinf(clip_limit)) return 1;
     if (user_range && (mode != ORC_GLOBAL || !(user_range[0] < user_range[1]))) return 1;
     if (redistribution < ORC_REDIST_EQUAL || redistribution > ORC_REDIST_INTEGER || rounds < 1) return 1;
     const int D = ndim, n = n_bins;
@@ -197,7 +214,7 @@ int mclahe_oracle_run_variant(int ndim, const int64_t *shape, const int64_t *ksi
     }
 
     /* Alg. 1 loop over kernels: range (AHR), histogram, clip, cdf, map. */
-    const int64_t C = (int64_t)floor((double)clip_limit * (double)K);
+    const int64_t C = oracle_clip_count(clip_limit, K);
 #pragma omp parallel for schedule(dynamic)
     for (int64_t k = 0; k < nker; ++k) {
         int64_t kc[ORC_MAX_DIM], rem = k;
@@ -337,7 +354,7 @@ int mclahe_oracle_run_variant(int ndim, const int64_t *shape, const int64_t *ksi
 
 /* The paper's method: equal redistribution once, centres at k*b + (b-1)/2. */
 int mclahe_oracle_run(int ndim, const int64_t *shape, const int64_t *ksize,
-                      int n_bins, float clip_limit, int mode,
+                      int n_bins, double clip_limit, int mode,
                       const float *user_range, int in_dtype, const void *in,
                       int out_dtype, void *out, int64_t *hist, int64_t *clipped,
                       float *lut, float *range, double *out_f64)

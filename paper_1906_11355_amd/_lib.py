@@ -85,7 +85,7 @@ def _load():
     P = ctypes.c_void_p
     i64p = ctypes.POINTER(ctypes.c_int64)
     sig = {
-        "mclahe_plan": [ctypes.POINTER(P), ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_float,
+        "mclahe_plan": [ctypes.POINTER(P), ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_double,
                         ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int],
         "mclahe_plan_destroy": [P],
         "mclahe_plan_geometry": [P, ctypes.POINTER(Geometry)],
@@ -183,7 +183,7 @@ class Plan:
         ur = None if self.user_range is None else (ctypes.c_float * 2)(*self.user_range)
         h = ctypes.c_void_p()
         _check(lib.mclahe_plan(ctypes.byref(h), len(self.shape), sh, ks, self.n_bins,
-                               ctypes.c_float(self.clip_limit), self.mode, ur, self.in_code,
+                               ctypes.c_double(self.clip_limit), self.mode, ur, self.in_code,
                                self.out_code))
         self._h = h
 

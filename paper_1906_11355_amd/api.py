@@ -33,6 +33,29 @@ def _check_tensor(x: torch.Tensor, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _check_against_plan(plan: Plan, x: torch.Tensor, out: torch.Tensor | None, what: str = ""):
+    """The C ABI receives raw pointers only: make sure the tensors are what the
+    plan describes, so that no kernel reads or writes past them."""
+    if tuple(x.shape) != plan.shape:
+        raise ValueError(f"{what}input shape {tuple(x.shape)} differs from the plan's {plan.shape}")
+    if _lib.dtype_code(x.dtype) != plan.in_code:
+        raise ValueError(f"{what}input dtype {x.dtype} differs from the plan's {TORCH_DTYPE[plan.in_code]}")
+    if out is not None:
+        if tuple(out.shape) != plan.shape:
+            raise ValueError(f"{what}output shape {tuple(out.shape)} differs from the plan's {plan.shape}")
+        if out.dtype != TORCH_DTYPE[plan.out_code]:
+            raise ValueError(f"{what}output dtype {out.dtype} differs from the plan's {TORCH_DTYPE[plan.out_code]}")
+        if out.device != x.device:
+            raise ValueError(f"{what}output is on {out.device}, input on {x.device}")
+
+
+def _check_workspace(ws: torch.Tensor, need: int, device):
+    if ws.device != device:
+        raise ValueError(f"workspace is on {ws.device}, input on {device}")
+    if ws.numel() * ws.element_size() < need:
+        raise ValueError(f"workspace holds {ws.numel() * ws.element_size()} bytes, {need} needed")
+
+
 def enhance(x: torch.Tensor, kernel_size: Sequence[int], n_bins: int = 256, clip_limit: float = 0.01,
             mode="global", user_range=None, out_dtype=torch.float32, plan: Plan | None = None,
             workspace: torch.Tensor | None = None, out: torch.Tensor | None = None,
@@ -44,10 +67,13 @@ def enhance(x: torch.Tensor, kernel_size: Sequence[int], n_bins: int = 256, clip
     need = plan.workspace_size()
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _check_tensor(workspace, "workspace")
+    _check_workspace(workspace, need, x.device)
     if out is None:
         out = torch.empty(x.shape, dtype=TORCH_DTYPE[plan.out_code], device=x.device)
     _check_tensor(out, "output")
-    plan.run_ptr(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+    _check_against_plan(plan, x, out)
+    plan.run_ptr(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                  stream_handle(x.device))
     return (out, workspace, plan) if return_workspace else out
 
@@ -81,16 +107,26 @@ def enhance_batched(xs: Sequence[torch.Tensor], params: Sequence[dict] | None = 
     """Enhance many volumes as one batch: one launch per pass over all volumes (hipGraph)."""
     if plans is None:
         plans = make_plans(xs, params)
-    for x in xs:
-        _check_tensor(x, "input")
+    if len(plans) != len(xs) or (outs is not None and len(outs) != len(xs)):
+        raise ValueError("one plan (and one output) per input volume")
+    dev = xs[0].device
+    for i, x in enumerate(xs):
+        _check_tensor(x, f"input {i}")
+        if x.device != dev:
+            raise ValueError(f"input {i} is on {x.device}, input 0 on {dev}")
     need = _lib.batched_workspace_size(plans)
     if workspace is None:
-        workspace = torch.empty(need, dtype=torch.uint8, device=xs[0].device)
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check_tensor(workspace, "workspace")
+    _check_workspace(workspace, need, dev)
     if outs is None:
         outs = [torch.empty(x.shape, dtype=TORCH_DTYPE[p.out_code], device=x.device)
                 for x, p in zip(xs, plans)]
+    for i, (p, x, o) in enumerate(zip(plans, xs, outs)):
+        _check_tensor(o, f"output {i}")
+        _check_against_plan(p, x, o, f"volume {i}: ")
     _lib.run_batched_ptr(plans, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs],
-                         workspace.data_ptr(), workspace.numel(), stream_handle(xs[0].device))
+                         workspace.data_ptr(), workspace.numel() * workspace.element_size(), stream_handle(dev))
     return (outs, workspace, plans) if return_workspace else outs
 
 

@@ -65,7 +65,7 @@ struct mclahe_plan_s {
     int D;
     int64_t shape[MC_MAXD], ks[MC_MAXD];
     int nb;
-    float clip;
+    double clip;
     int mode;
     int has_ur;
     float ur[2];
@@ -73,20 +73,35 @@ struct mclahe_plan_s {
     McAxis ax[MC_MAXD];
     int64_t stride[MC_MAXD];
     int64_t nvox, nker, K, clipC, ncells;
-    mclahe_tuning tune;  // requested (0 = default)
+    mclahe_tuning tune;   // requested for per-volume runs (0 = default)
+    mclahe_tuning btune;  // requested for batched runs (0 = default)
     int redist = MC_REDIST_EQUAL, rounds = 1, centre_half = 0;   // method variant
-    McVol v;             // derived descriptor (no pointers)
-    // workspace layout
+    // Derived work decompositions (descriptors without pointers).  Vector
+    // loads need 16-byte aligned buffers and bound how long a unit's row
+    // segment may be (MC_T chunks of V elements); buffers at any other
+    // address take the scalar decomposition, whose segments fit MC_T single
+    // elements.  Batched launches default to coarser units (many volumes
+    // fill the chip together).
+    McVol v, v1;     // per-volume runs: vector loads, scalar loads
+    McVol bv, bv1;   // batched runs: vector loads, scalar loads
+    // one workspace layout serves all four decompositions
     uint64_t o_part, o_rpart, o_hist, o_clipped, o_lut, o_range, o_scale, total;
-    size_t lds_range, lds_hist, lds_clip, lds_map;
-    // the same for batched launches, whose default work units are coarser
-    // (many volumes fill the chip together)
-    struct {
-        McVol v;
-        uint64_t o_part, o_rpart, o_hist, o_clipped, o_lut, o_range, o_scale, total;
-        size_t lds_range, lds_hist, lds_clip, lds_map;
-    } bd;
 };
+
+// Clip count C = floor(clip * K) (Algorithm 1's clip limit as a fraction of
+// the kernel's voxel count).  A clip limit is written as a decimal whose
+// binary value may fall a rounding error short of it (0.02 * 270000 must
+// give 5400, 0.29 * 100 must give 29), so a product within a relative 2^-40
+// below an integer counts as that integer; C is capped at K (at K or above
+// no bin is clipped).
+static int64_t clip_count(double clip, int64_t K)
+{
+    const double c = clip * (double)K;
+    if (!(c < (double)K)) return K;   // no bin can exceed K: nothing is clipped
+    int64_t C = (int64_t)c;
+    if ((double)(C + 1) - c <= std::ldexp(c, -40)) ++C;
+    return C;
+}
 
 // Default minimum voxels per histogram / interpolation work unit: a unit's
 // fixed cost (staging and flushing its LDS arrays) dominates smaller ones.
@@ -134,11 +149,12 @@ static void seg_extent(const McAxis &a, int kA, int kB, int &xs, int &xe)
 // Chunks of V elements a segment [xs, xe) spans.
 static int seg_chunks(int xs, int xe, int V) { return (xe + V - 1) / V - xs / V; }
 
-// Derive the work decomposition and workspace layout from the tuning, with
-// default work units of at least unit_vox voxels.
-static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox, int64_t min_map_cols)
+// Derive a work decomposition from tuning t, with default work units of at
+// least unit_vox voxels, for vector loads (vector: chunks of mc_vec_elems
+// elements when the last axis is a multiple of it) or scalar loads.
+static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t, int64_t unit_vox,
+                                 int64_t min_map_cols, bool vector, McVol &v)
 {
-    McVol &v = p->v;
     memset(&v, 0, sizeof v);
     const int D = p->D;
     v.D = D;
@@ -161,10 +177,9 @@ static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox, int64_t min
     v.nker = p->nker;
     const McAxis &al = p->ax[D - 1];
     const int vmax = mc_vec_elems((int)esize(p->in_dt));
-    const int V = (al.s % vmax == 0) ? vmax : 1;
+    const int V = (vector && al.s % vmax == 0) ? vmax : 1;
     v.vec = V;
     const int maxchunks = MC_T - 1;
-    const mclahe_tuning &t = p->tune;
 
     // ---- histogram units --------------------------------------------------
     int R = t.hist_copies > 0 ? t.hist_copies : 1;   // 1 replica: fastest measured on Poisson counts
@@ -374,11 +389,44 @@ static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox, int64_t min
     if (nmu >= (int64_t)1 << 31) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "too many map units");
     v.n_map_wu = (uint32_t)nmu;
 
-    // ---- workspace layout -------------------------------------------------
-    // The per-kernel arrays come first: their offsets depend only on the
-    // problem, so they are the same in the plain and the batched
-    // decomposition; the per-unit partials, whose sizes depend on the work
-    // units, come last.
+    return MCLAHE_SUCCESS;
+}
+
+// Words of the per-unit partial histograms and floats of the range partials
+// a decomposition writes.
+static uint64_t part_words(const McVol &v) { return (uint64_t)v.n_hist_wu * v.hG * v.nb; }
+static uint64_t rpart_floats(const McVol &v)
+{
+    return v.mode == MC_GHR ? (uint64_t)std::max<uint32_t>(v.n_range_wu, 1) * 2 : (uint64_t)v.n_hist_wu * v.hG * 2;
+}
+
+// LDS bytes of pass ph (0 range, 1 histogram, 2 clip, 3 map) under v.
+static size_t pass_lds(const mclahe_plan_s *p, const McVol &v, int ph)
+{
+    const size_t hist = hist_lds_header() + (size_t)v.hG * mc_hist_slot_stride(v.nb, v.hR) * 4;
+    switch (ph) {
+    case 0: return p->mode == MC_AHR ? hist : 2 * MC_T * 4;
+    case 1: return hist;
+    case 2: return MC_T * 8;
+    default: return v.path == 0 ? map_otab_bytes(p->D) + map_lut_bytes(p, v.mG) : 0;
+    }
+}
+
+// All four decompositions, then one workspace layout that fits each of them.
+// The per-kernel arrays come first (their offsets depend only on the
+// problem), the per-unit partials last, sized for the largest decomposition.
+static mclahe_status derive(mclahe_plan_s *p)
+{
+    mclahe_status s;
+    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, true, p->bv))) return s;
+    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, false, p->bv1))) return s;
+    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, true, p->v))) return s;
+    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, false, p->v1))) return s;
+    uint64_t pw = 0, rf = 0;
+    for (const McVol *d : {&p->v, &p->v1, &p->bv, &p->bv1}) {
+        pw = std::max(pw, part_words(*d));
+        rf = std::max(rf, rpart_floats(*d));
+    }
     uint64_t o = 0;
     p->o_hist = o;
     o = align256(o + (uint64_t)p->nker * p->nb * 4);
@@ -391,65 +439,32 @@ static mclahe_status derive_core(mclahe_plan_s *p, int64_t unit_vox, int64_t min
     p->o_scale = o;
     o = align256(o + (p->mode == MC_AHR ? (uint64_t)p->nker : 1) * 4);
     p->o_part = o;
-    o = align256(o + (uint64_t)v.n_hist_wu * v.hG * v.nb * 4);
+    o = align256(o + pw * 4);
     p->o_rpart = o;
-    const uint64_t nrp = p->mode == MC_GHR ? (uint64_t)std::max<uint32_t>(v.n_range_wu, 1) * 2
-                                           : (uint64_t)v.n_hist_wu * v.hG * 2;
-    o = align256(o + nrp * 4);
+    o = align256(o + rf * 4);
     p->total = o;
-
-    p->lds_range = 2 * MC_T * 4;
-    p->lds_hist = hdr + (size_t)v.hG * mc_hist_slot_stride(v.nb, v.hR) * 4;
-    p->lds_clip = MC_T * 8;
-    p->lds_map = fast ? otab + map_lut_bytes(p, v.mG) : 0;
     return MCLAHE_SUCCESS;
 }
 
-// Both decompositions: the batched one (kept in p->bd), then the plain one.
-static mclahe_status derive(mclahe_plan_s *p)
+// Vector loads and stores need both buffers on 16-byte boundaries.
+static bool vec_aligned(const void *in, const void *out)
 {
-    mclahe_status s = derive_core(p, kUnitVoxBatch, 1);
-    if (s) return s;
-    p->bd.v = p->v;
-    p->bd.o_part = p->o_part;
-    p->bd.o_rpart = p->o_rpart;
-    p->bd.o_hist = p->o_hist;
-    p->bd.o_clipped = p->o_clipped;
-    p->bd.o_lut = p->o_lut;
-    p->bd.o_range = p->o_range;
-    p->bd.o_scale = p->o_scale;
-    p->bd.total = p->total;
-    p->bd.lds_range = p->lds_range;
-    p->bd.lds_hist = p->lds_hist;
-    p->bd.lds_clip = p->lds_clip;
-    p->bd.lds_map = p->lds_map;
-    return derive_core(p, kUnitVoxPlain, kMinMapCols);
+    return ((uintptr_t)in % 16) == 0 && ((uintptr_t)out % 16) == 0;
 }
 
-// A copy of the plan that carries the batched decomposition, for the
+// A copy of the plan that carries the batched decompositions, for the
 // batched entry points (same problem, same bits, coarser default units).
 static void batch_view(const mclahe_plan_s *p, mclahe_plan_s &q)
 {
     q = *p;
-    q.v = p->bd.v;
-    q.o_part = p->bd.o_part;
-    q.o_rpart = p->bd.o_rpart;
-    q.o_hist = p->bd.o_hist;
-    q.o_clipped = p->bd.o_clipped;
-    q.o_lut = p->bd.o_lut;
-    q.o_range = p->bd.o_range;
-    q.o_scale = p->bd.o_scale;
-    q.total = p->bd.total;
-    q.lds_range = p->bd.lds_range;
-    q.lds_hist = p->bd.lds_hist;
-    q.lds_clip = p->bd.lds_clip;
-    q.lds_map = p->bd.lds_map;
+    q.v = p->bv;
+    q.v1 = p->bv1;
 }
 
 // Pointers of a run's descriptor.
 static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, char *ws)
 {
-    v = p->v;
+    v = vec_aligned(in, out) ? p->v : p->v1;
     v.in = in;
     v.out = out;
     v.part = (uint32_t *)(ws + p->o_part);
@@ -459,9 +474,6 @@ static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, ch
     v.lut = (float *)(ws + p->o_lut);
     v.range = (float *)(ws + p->o_range);
     v.scale = (float *)(ws + p->o_scale);
-    const size_t es_in = esize(p->in_dt);
-    if (v.vec > 1 && (((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0)) v.vec = 1;
-    (void)es_in;
 }
 
 // Kernel selection lives in the per-dtype translation units (k_plain_*.hip).
@@ -486,24 +498,19 @@ static KPair phase_kernels(const mclahe_plan_s *p, const McVol &v, int ph, size_
 {
     const int dt = p->in_dt;
     const bool ahr = p->mode == MC_AHR;
+    lds = pass_lds(p, v, ph);
     switch (ph) {
     case 0:
-        if (ahr) {
-            lds = p->lds_hist;
+        if (ahr)
             return dt == MC_U8 ? mc_pick_hist_u8(true, true, 0)
                  : dt == MC_U16 ? mc_pick_hist_u16(true, true, 0) : mc_pick_hist_f32(true, true, 0);
-        }
-        lds = p->lds_range;
         return dt == MC_U8 ? mc_pick_range_u8() : dt == MC_U16 ? mc_pick_range_u16() : mc_pick_range_f32();
     case 1:
-        lds = p->lds_hist;
         return dt == MC_U8 ? mc_pick_hist_u8(ahr, false, v.hPeel)
              : dt == MC_U16 ? mc_pick_hist_u16(ahr, false, v.hPeel) : mc_pick_hist_f32(ahr, false, v.hPeel);
     case 2:
-        lds = p->lds_clip;
         return KPair{(KFn)k_clip, (KFnB)k_clip_b, MC_T};
     default:
-        lds = p->lds_map;
         return dt == MC_U8 ? mc_pick_map_u8(p->D, ahr, v.path)
              : dt == MC_U16 ? mc_pick_map_u16(p->D, ahr, v.path) : mc_pick_map_f32(p->D, ahr, v.path);
     }
@@ -624,8 +631,12 @@ static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
             g.range_parts += u;
         }
     }
-    const McVol &v = p->v;
-    const int64_t nhu = (int64_t)L * g.cols_per_layer * v.hS * v.hCr;
+    // partials of the slab's histogram units, for either decomposition (a
+    // slab buffer is vector-aligned whenever vector loads are possible, but
+    // the scalar one is sized too)
+    int64_t nhg = 0;
+    for (const McVol *v : {&p->v, &p->v1})
+        nhg = std::max<int64_t>(nhg, (int64_t)L * g.cols_per_layer * v->hS * v->hCr * v->hG);
     const int64_t nk = (int64_t)L * g.layer_kernels;
     uint64_t o = 0;
     g.o_in = o;   // two slab buffers, used alternately (halo rows pass from one to the next)
@@ -637,10 +648,10 @@ static mclahe_status chunk_geom(const mclahe_plan_s *p, int L, ChunkGeom &g)
     g.o_out2 = o;
     o = align256(o + (uint64_t)g.max_out_rows * g.row_elems * esize(p->out_dt));
     g.o_part = o;
-    o = align256(o + (uint64_t)nhu * v.hG * p->nb * 4);
+    o = align256(o + (uint64_t)nhg * p->nb * 4);
     g.o_rpart = o;
     o = align256(o + (p->mode == MC_GHR ? (uint64_t)std::max<uint32_t>(g.range_parts, 1) * 2
-                                        : (uint64_t)nhu * v.hG * 2) * 4);
+                                        : (uint64_t)nhg * 2) * 4);
     g.o_hist = o;
     o = align256(o + (uint64_t)nk * p->nb * 4);
     g.o_clipped = o;
@@ -779,12 +790,15 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
                                   (size_t)(g.hr0[j] - base) * row_in, hipMemcpyDeviceToDevice, cs->h2d));
         }
         if ((s = upload(X, g.hr0[j] - base, g.hr0[j], g.hr1[j]))) return s;
-        McVol v = p->v;
+        // the slab's buffers index global rows; vector loads need them aligned
+        const char *sin = cur - (size_t)base * row_in;
+        char *sout = outbuf[Y] - (size_t)g.mr0[j] * row_out;
+        McVol v = vec_aligned(sin, sout) ? p->v : p->v1;
         v.wk0 = kA;
         v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
         v.n_clip_wu = (uint32_t)((int64_t)nl * g.layer_kernels);
         v.n_range_wu = g.range_parts;
-        v.in = cur - (size_t)base * row_in;           // global rows index the slab
+        v.in = sin;
         v.out = nullptr;
         v.part = (uint32_t *)(ws + g.o_part);
         v.rpart = (float *)(ws + g.o_rpart);
@@ -798,7 +812,6 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             v.range = (float *)(ws + g.o_range);
             v.scale = (float *)(ws + g.o_scale);
         }
-        if (v.vec > 1 && ((uintptr_t)v.in % 16)) v.vec = 1;
         for (int ph = 0; ph < 3; ++ph) {
             const KPair k = phase_kernels(p, v, ph, lds);
             if (ph == 0 && !ahr) continue;            // GHR range done above
@@ -810,16 +823,14 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             McVol m = v;
             m.wc0 = cA;
             m.n_map_wu = (uint32_t)((int64_t)(cB - cA) * g.mcols_per_layer * v.mS * v.mU);
-            m.in = cur - (size_t)base * row_in;
-            m.out = outbuf[Y] - (size_t)g.mr0[j] * row_out;
+            m.in = sin;
+            m.out = sout;
             // LUT layer 0 of the buffer is global kernel layer kA - 1
             m.lut = lutb - (int64_t)(kA - 1) * (int64_t)layer_lut;
             if (ahr) {
                 m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
                 m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
             }
-            m.vec = p->v.vec;
-            if (m.vec > 1 && (((uintptr_t)m.in % 16) || ((uintptr_t)m.out % 16))) m.vec = 1;
             if (out_used[Y]) HIPCHK(hipStreamWaitEvent(st, cs->out_free[Y], 0));
             const KPair k = phase_kernels(p, m, 3, lds);
             if ((s = launch(k.plain, m.n_map_wu, k.threads, lds, st, m))) return s;
@@ -869,13 +880,20 @@ struct BatchLayout {
     uint32_t n_idx = 0;
 };
 
-static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, BatchLayout &L)
+// ins / outs (may be NULL: sizing only) pick each volume's decomposition:
+// vector loads for 16-byte aligned buffers, scalar loads otherwise.  Sizes
+// and offsets do not depend on them.
+static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, const void *const *ins,
+                                  void *const *outs, BatchLayout &L)
 {
     if (n < 1 || !plans) return fail(MCLAHE_ERROR_INVALID_VALUE, "batched call needs n >= 1 plans");
     for (int i = 0; i < n; ++i)
         if (!plans[i]) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan %d is NULL", i);
     L.view.resize(n);
-    for (int i = 0; i < n; ++i) batch_view(plans[i], L.view[i]);
+    for (int i = 0; i < n; ++i) {
+        batch_view(plans[i], L.view[i]);
+        if (ins && outs && !vec_aligned(ins[i], outs[i])) L.view[i].v = L.view[i].v1;
+    }
     // group the volumes of each pass by kernel class
     L.launches.clear();
     for (int ph = 0; ph < MC_PHASES; ++ph) {
@@ -1155,7 +1173,7 @@ const char *mclahe_status_string(mclahe_status s)
 const char *mclahe_last_error(void) { return g_err.c_str(); }
 
 mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, const int64_t *kernel_size,
-                          int n_bins, float clip_limit, mclahe_range_mode mode, const float *user_range,
+                          int n_bins, double clip_limit, mclahe_range_mode mode, const float *user_range,
                           mclahe_dtype in_dtype, mclahe_dtype out_dtype)
 {
     g_err.clear();
@@ -1164,7 +1182,7 @@ mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, c
     if (ndim < 1 || ndim > MC_MAXD) return fail(MCLAHE_ERROR_INVALID_VALUE, "ndim must be in 1..8 (got %d)", ndim);
     if (!shape || !kernel_size) return fail(MCLAHE_ERROR_INVALID_VALUE, "shape/kernel_size is NULL");
     if (n_bins < 2 || n_bins > 8192) return fail(MCLAHE_ERROR_INVALID_VALUE, "n_bins must be in 2..8192 (got %d)", n_bins);
-    if (!(clip_limit >= 0.0f) || std::isinf(clip_limit))
+    if (!(clip_limit >= 0.0) || std::isinf(clip_limit))
         return fail(MCLAHE_ERROR_INVALID_VALUE, "clip_limit must be finite and >= 0");
     if (mode != MCLAHE_RANGE_GLOBAL && mode != MCLAHE_RANGE_KERNEL)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "unknown range mode %d", (int)mode);
@@ -1234,8 +1252,9 @@ mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, c
         st *= p->shape[i];
     }
     for (int i = ndim; i < MC_MAXD; ++i) p->stride[i] = 0;
-    p->clipC = (int64_t)std::floor((double)clip_limit * (double)p->K);
+    p->clipC = clip_count(clip_limit, p->K);
     memset(&p->tune, 0, sizeof p->tune);
+    memset(&p->btune, 0, sizeof p->btune);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_load();
@@ -1456,7 +1475,7 @@ mclahe_status mclahe_batched_workspace_size(int n, const mclahe_plan_t *plans, s
 {
     if (!bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
     BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
+    mclahe_status s = batch_layout(n, plans, nullptr, nullptr, L);
     if (s) return s;
     *bytes = L.total;
     return MCLAHE_SUCCESS;
@@ -1466,7 +1485,7 @@ mclahe_status mclahe_batched_workspace_offsets(int n, const mclahe_plan_t *plans
 {
     if (!offsets) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
     BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
+    mclahe_status s = batch_layout(n, plans, nullptr, nullptr, L);
     if (s) return s;
     for (int i = 0; i < n; ++i) offsets[i] = L.vol_off[i];
     return MCLAHE_SUCCESS;
@@ -1476,7 +1495,7 @@ mclahe_status mclahe_batched_table_size(int n, const mclahe_plan_t *plans, size_
 {
     if (!bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
     BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
+    mclahe_status s = batch_layout(n, plans, nullptr, nullptr, L);
     if (s) return s;
     *bytes = L.o_first - L.o_table;
     return MCLAHE_SUCCESS;
@@ -1493,10 +1512,10 @@ mclahe_status mclahe_batched_table(int n, const mclahe_plan_t *plans, const void
                                    size_t *needed)
 {
     g_err.clear();
-    BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
-    if (s) return s;
     if (!d_in || !d_out || !needed) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, d_in, d_out, L);
+    if (s) return s;
     std::vector<char *> vws;
     vol_ws_in_place(n, (char *)d_ws, L, vws);
     std::vector<char> img;
@@ -1603,10 +1622,10 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
                                  void *const *d_out, void *d_ws, size_t wsb, void *stream)
 {
     g_err.clear();
-    BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
-    if (s) return s;
     if (!d_in || !d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output arrays are NULL");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, d_in, d_out, L);
+    if (s) return s;
     for (int i = 0; i < n; ++i) {
         s = check_run_args(plans[i], d_in[i], d_out[i], d_ws, wsb, L.total);
         if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
@@ -1624,14 +1643,13 @@ mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans, const 
                                        void *d_table, size_t table_bytes, void *stream)
 {
     g_err.clear();
-    BatchLayout L;
-    mclahe_status s = batch_layout(n, plans, L);
-    if (s) return s;
     if (!d_in || !d_out || !d_ws || !ws_bytes)
         return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output/workspace arrays are NULL");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, d_in, d_out, L);
+    if (s) return s;
     for (int i = 0; i < n; ++i) {
-        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws[i], ws_bytes[i],
-                           std::max<uint64_t>(plans[i]->total, L.view[i].total));
+        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws[i], ws_bytes[i], plans[i]->total);
         if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
     }
     const size_t tb = L.o_first - L.o_table;

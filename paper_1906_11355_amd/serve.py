@@ -330,6 +330,9 @@ class Server:
                 try:
                     token = b.launch(batch, s)
                 except Exception as e:       # a HIP error fails this step's requests
+                    # part of the step may already be queued: its blocks are
+                    # released only after that work has left the stream
+                    b.drain(s)
                     for r in batch:
                         r.status, r.error = FAILED, str(e)
                         self.arena.free(r.off)
@@ -475,6 +478,10 @@ class DeviceBackend:
             r.result["out_bytes"] = self.arena[o:o + nout].cpu()
             r.result["ws_bytes"] = self.arena[w:w + self.plan(r).workspace_size()].cpu()
         r.dev.pop("ev", None)
+
+    def drain(self, s: int) -> None:
+        """Wait until everything queued on compute stream s has run."""
+        self.streams[s].synchronize()
 
     def wait(self, deadline: Optional[float], busy: bool) -> None:
         # poll_s = 0: busy-poll (a serving loop owns a host core)

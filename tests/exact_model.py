@@ -47,6 +47,13 @@ def f32_bin(v, lo, hi, n: int) -> int:
     return int(t)
 
 
+def decimal_clip_count(clip: float, K: int) -> int:
+    """Clip count of a clip limit read as the decimal that was written: the
+    shortest decimal that round-trips to the double, times K, floored, and
+    capped at K (at K or above nothing is clipped)."""
+    return min(math.floor(Fraction(repr(float(clip))) * K), K)
+
+
 def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
                  adaptive: bool = False, user_range=None, repeated_rounds: int = 1,
                  centre_half: bool = False):
@@ -64,8 +71,7 @@ def exact_mclahe(x: np.ndarray, kernel_size, n: int, clip: float,
     nk = [padded.shape[i] // b[i] for i in range(D)]
     assert all(padded.shape[i] == nk[i] * b[i] for i in range(D))
     K = int(np.prod(b))
-    clipf = np.float32(clip)
-    C = math.floor(Fraction(float(clipf)) * K)
+    C = decimal_clip_count(clip, K)
 
     if user_range is not None:
         glo, ghi = np.float32(user_range[0]), np.float32(user_range[1])

@@ -18,6 +18,7 @@ import pytest
 import oracle
 from paper_1906_11355_amd import _lib
 from paper_1906_11355_amd._lib import MclaheError, Plan
+from exact_model import decimal_clip_count
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mclahe.h")
@@ -81,8 +82,19 @@ def test_geometry_matches_oracle():
         assert g["n_kernels_axis"] == nk.tolist()
         assert g["n_kernels"] == int(np.prod(nk))
         assert g["kernel_voxels"] == int(np.prod(ks))
-        assert g["clip_count"] == int(np.floor(np.float64(np.float32(0.3)) * np.prod(ks)))
+        assert g["clip_count"] == decimal_clip_count(0.3, int(np.prod(ks)))
         assert g["n_cells"] == int(np.prod(nk - 1))
+
+
+@pytest.mark.parametrize("clip,ks,C", [
+    (0.02, (30, 30, 15, 20), 5400),   # the photoemission experiment (Sec. IV.A)
+    (0.01, (10, 10), 1),
+    (0.29, (100,), 29),
+    (2.0, (4, 4), 16),
+])
+def test_clip_count_of_decimal_limits(clip, ks, C):
+    shape = tuple(2 * b for b in ks)
+    assert Plan(shape, ks, 16, clip).geometry()["clip_count"] == C
 
 
 def test_workspace_layout_and_tuning():
@@ -329,6 +341,48 @@ def test_batched_table_decodes_every_unit_once():
         assert ptrs[3 * i] == ins[i] and ptrs[3 * i + 1] == outs[i]
         assert ptrs[3 * i + 2] == ws + offs[i] + p.layout()["hist"]
     assert counts[0 * n + n - 1] == 0                              # user range: no range pass
+
+
+@pytest.mark.parametrize("in_off,out_off", [(0, 0), (1, 0), (4, 0), (0, 8), (2, 2)])
+def test_batched_units_fit_their_work_groups(in_off, out_off):
+    """Buffers off a 16-byte boundary switch a volume to scalar loads; its row
+    segments must then fit MC_T single elements (histogram) and the
+    interpolation work-group (512 threads under a global range with vector
+    loads' LDS staging, 256 otherwise), not the vector chunks the aligned
+    decomposition was sized for."""
+    d = tempfile.mkdtemp(prefix="mclahe_batch_probe_")
+    so = os.path.join(d, "probe.so")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC",
+                           "-I", os.path.join(ROOT, "paper_1906_11355_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "batch_probe.cpp"), "-o", so])
+    probe = ctypes.CDLL(so)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    probe.probe_batch_chunks.argtypes = [ctypes.c_char_p, ctypes.c_size_t, u32p, u32p, u32p]
+    probe.probe_batch_chunks.restype = ctypes.c_int
+    plans = [Plan((512, 512), (64, 64), 256, 0.01, in_dtype="uint8"),
+             Plan((64, 2048), (16, 256), 256, 0.02, in_dtype="uint16"),
+             Plan((40, 1040), (16, 260), 128, 0.03),
+             Plan((40, 1040), (16, 260), 128, 0.03, "kernel"),
+             Plan((6, 10, 520), (3, 5, 130), 64, 0.05),
+             Plan((24, 1536), (8, 512), 256, 0.02, "kernel", out_dtype="uint8"),
+             Plan((6, 4096), (3, 4096), 256, 0.01, in_dtype="uint8"),
+             Plan((256, 256, 128, 32), (32, 32, 16, 8), 512, 0.02)]
+    from paper_1906_11355_amd import synth
+    plans += [Plan(s["shape"], s["kernel_size"], 256, s["clip_limit"], "kernel" if s["adaptive"] else "global",
+                   in_dtype="uint16" if s["kind"] == "2d" else "float32") for s in synth.mix_spec(16, 4)]
+    n = len(plans)
+    ins = [(1 << 36) + i * (1 << 30) + in_off for i in range(n)]
+    outs = [(1 << 37) + i * (1 << 30) + out_off for i in range(n)]
+    img = _lib.batched_table(plans, ins, outs, 1 << 40)
+    hm, mm, vec = ((ctypes.c_uint32 * n)() for _ in range(3))
+    assert probe.probe_batch_chunks(img, len(img), hm, mm, vec) == 0
+    aligned = in_off % 16 == 0 and out_off % 16 == 0
+    for i, p in enumerate(plans):
+        if not aligned:
+            assert vec[i] == 1, i
+        map_threads = 512 if p.mode == _lib.GLOBAL else 256
+        assert 1 <= hm[i] <= 256, (i, hm[i])
+        assert mm[i] <= map_threads, (i, mm[i])
 
 
 # ---------------------------------------------------------------- metrics --

@@ -121,6 +121,34 @@ def test_unaligned_pointers_and_rows():
     _case(z, (9, 16), 256, 0.03, in_offset=1, out_offset=4)
 
 
+@pytest.mark.parametrize("case", range(6))
+def test_unaligned_buffers_with_long_rows(case):
+    """Buffers off a 16-byte boundary take scalar loads, whose work units must
+    then fit a last-axis segment of single elements: segments of 512 to 2048
+    voxels (valid only for vector chunks) are re-split, not left unprocessed."""
+    rng = np.random.default_rng(50 + case)
+    if case == 0:    # 2D uint8 512x512, kernel 64x64: one 512-voxel segment for 8-voxel chunks
+        x, ks, nb, clip, mode, off = (rng.integers(0, 256, (512, 512)).astype(np.uint8), (64, 64), 256, 0.01,
+                                      "global", (1, 0))
+    elif case == 1:  # 2D uint16 64x2048, kernel 16x256: 1920-voxel segments
+        x, ks, nb, clip, mode, off = (rng.integers(0, 60000, (64, 2048)).astype(np.uint16), (16, 256), 256, 0.02,
+                                      "global", (2, 0))
+    elif case == 2:  # float32 rows of 1040 with 260-voxel kernels, input off by 4 bytes
+        x, ks, nb, clip, mode, off = (rng.poisson(6.0, (40, 1040)).astype(np.float32), (16, 260), 128, 0.03,
+                                      "global", (4, 0))
+    elif case == 3:  # the same, adaptive range, output off by 8 bytes
+        x, ks, nb, clip, mode, off = (rng.poisson(6.0, (40, 1040)).astype(np.float32), (16, 260), 128, 0.03,
+                                      "kernel", (0, 8))
+    elif case == 4:  # 3D float32, last axis 520
+        x, ks, nb, clip, mode, off = (rng.poisson(3.0, (6, 10, 520)).astype(np.float32), (3, 5, 130), 64, 0.05,
+                                      "global", (4, 4))
+    else:            # uint8 out of a float32 volume, both buffers off
+        x, ks, nb, clip, mode, off = (rng.poisson(4.0, (24, 1536)).astype(np.float32), (8, 512), 256, 0.02,
+                                      "kernel", (12, 1))
+    od = np.uint8 if case == 5 else np.float32
+    _case(x, ks, nb, clip, mode, out_dtype=od, in_offset=off[0], out_offset=off[1])
+
+
 @pytest.mark.parametrize("dtype,in_offset", [(np.float32, 0), (np.float32, 4), (np.uint16, 0), (np.uint8, 0),
                                              (np.uint8, 3)])
 def test_global_range_many_units_ragged_tiles(dtype, in_offset):

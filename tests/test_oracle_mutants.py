@@ -23,8 +23,7 @@ MUTANTS = {
     "reflect_not_symmetric": ("if (x < 0) x = -x - 1;", "if (x < 0) x = -x;"),
     "excess_dropped": ("H[j] = (int64_t)n * (H[j] < Cr ? H[j] : Cr) + E;",
                        "H[j] = (int64_t)n * (H[j] < Cr ? H[j] : Cr);"),
-    "clip_ceil": ("(int64_t)floor((double)clip_limit * (double)K)",
-                  "(int64_t)ceil((double)clip_limit * (double)K)"),
+    "clip_ceil": ("int64_t C = (int64_t)floor(c);", "int64_t C = (int64_t)ceil(c);"),
     "cdf_exclusive": ("acc += H[j];\n            double m", "double m"),
     "weights_swapped": ("coef *= bit ? w[i] : 1.0 - w[i];", "coef *= bit ? 1.0 - w[i] : w[i];"),
     "centre_b_over_2": ("(centre_half ? 2 * (ksize[i] / 2) : ksize[i] - 1)",

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from exact_model import exact_mclahe, f32_bin, pad_lengths
+from exact_model import decimal_clip_count, exact_mclahe, f32_bin, pad_lengths
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -196,6 +196,39 @@ def test_clip_closed_forms():
     for h, H in zip(rc["hist"], rc["clipped"]):
         E = np.maximum(h - C, 0).sum()
         assert (H == n * np.minimum(h, C) + E).all()
+
+
+def _oracle_clip_count(clip, K):
+    """C read back from the oracle: a constant 1D volume with kernel K puts all
+    K voxels of every kernel in bin 0, so every other bin holds the excess
+    share K - C (in units of 1/n)."""
+    r = oracle.run(np.full(K, 7.0, np.float32), (K,), 4, clip)
+    return K - int(r["clipped"][0, 1])
+
+
+@pytest.mark.parametrize("clip,K,C", [
+    (0.02, 270000, 5400),    # the photoemission experiment's clip limit and kernel (Sec. IV.A)
+    (0.01, 100, 1),          # float32(0.01) * 100 would floor to 0
+    (0.29, 100, 29),         # the double product 28.999999999999996 floors to 28
+    (0.25, 1000, 250),       # the fluorescence experiment's clip limit (Sec. IV.B), exact in binary
+    (0.7, 10, 7),
+    (1.0, 64, 64), (3.5, 64, 64),   # at or above K nothing is clipped: C is reported as K
+    (0.0, 64, 0),
+])
+def test_clip_count_of_decimal_limits(clip, K, C):
+    assert decimal_clip_count(clip, K) == C
+    assert _oracle_clip_count(clip, K) == C
+
+
+def test_clip_count_random_decimals():
+    """The oracle's count equals the written decimal's exact count, floored,
+    for decimals of 1-4 significant digits (exact rational arithmetic)."""
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        digits = int(rng.integers(1, 5))
+        clip = float(f"{rng.uniform(0.001, 0.999):.{digits}g}")
+        K = int(rng.choice([7, 64, 100, 300, 1000, 4096, 12000]))
+        assert _oracle_clip_count(clip, K) == decimal_clip_count(clip, K), (clip, K)
 
 
 def test_lut_invariants():

@@ -30,6 +30,8 @@ class SimBackend:
         self.live = {}          # rid -> bytes between stage and finish
         self.max_live = 0
         self.launches = []      # (stream, start, end, rids)
+        self.stages = []        # (time, arena offset, bytes)
+        self.partial = []       # failed steps: (end of their queued part, [(offset, bytes)])
 
     def clock(self):
         return self.t
@@ -43,6 +45,7 @@ class SimBackend:
         self.copy_free = max(self.t, self.copy_free) + r.voxels * 4 * self.t_copy
         r.dev["copy_done"] = self.copy_free
         r.dev["off"] = off
+        self.stages.append((self.t, off, r.need))
         self.live[r.rid] = r.need
         self.max_live = max(self.max_live, sum(self.live.values()))
 
@@ -50,6 +53,12 @@ class SimBackend:
         k = self.nlaunch
         self.nlaunch += 1
         if k in self.fail_steps:
+            # the first half of the step was queued before the error
+            done_part = reqs[:len(reqs) // 2]
+            if done_part:
+                start = max([self.t, self.stream_free[s]] + [r.dev["copy_done"] for r in done_part])
+                self.stream_free[s] = start + self.t_fixed + self.t_vox * sum(r.voxels for r in done_part)
+            self.partial.append((len(self.stages), self.stream_free[s], [(r.dev["off"], r.need) for r in reqs]))
             for r in reqs:
                 self.live.pop(r.rid, None)
             raise RuntimeError("injected HIP error")
@@ -73,6 +82,9 @@ class SimBackend:
 
     def finish(self, r):
         self.live.pop(r.rid, None)
+
+    def drain(self, s):
+        self.t = max(self.t, self.stream_free[s])
 
     def wait(self, deadline, busy):
         c = [tok[0] for tok in self.inflight if tok[0] > self.t]
@@ -227,6 +239,26 @@ def test_failed_step_frees_its_requests_only():
     assert failed and rep.n_failed == len(failed) <= 3
     assert rep.n_done == 40 - len(failed)
     assert all("injected" in r.error for r in failed)
+    assert srv.arena.used == 0
+
+
+def test_failed_step_keeps_its_blocks_until_queued_work_ends():
+    """A step that fails after queueing part of its work releases its arena
+    blocks only once that work has run: no request staged after the failure
+    lands in those blocks earlier."""
+    b = SimBackend(t_vox=1e-8)
+    srv = Server(b, 32 << 20, max_slots=8, max_batch=4)
+    reqs = _reqs(60, 20000.0, seed=8, sizes=(100000, 400000))
+    b.fail_steps = {1, 4}
+    srv.run(reqs)
+    assert len(b.partial) == 2
+    reused = 0
+    for first, end, blocks in b.partial:
+        for t, off, size in b.stages[first:]:
+            if any(off < o + n and o < off + size for o, n in blocks):
+                reused += 1
+                assert t >= end, (t, end)
+    assert reused > 0                      # the case is exercised
     assert srv.arena.used == 0
 
 

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from exact_model import exact_mclahe
+from exact_model import decimal_clip_count, exact_mclahe
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLD = json.load(open(os.path.join(HERE, "golden", "variants_1d.json")))
@@ -83,7 +83,7 @@ def test_integer_redistribution_invariants(seed):
     n, clip = 7, 0.1
     r = oracle.run(x, ks, n, clip, redistribution=oracle.INTEGER)
     K = int(np.prod(ks))
-    C = int(np.floor(np.float64(np.float32(clip)) * K))
+    C = decimal_clip_count(clip, K)
     for h, H in zip(r["hist"], r["clipped"]):
         base = np.minimum(h, C)
         E = int((h - base).sum())
