@@ -202,6 +202,24 @@ mclahe_status mclahe_workspace_layout(mclahe_plan_t plan, mclahe_layout *layout)
 mclahe_status mclahe_run(mclahe_plan_t plan, const void *d_in, void *d_out,
                          void *d_workspace, size_t workspace_bytes, void *hip_stream);
 
+/* mclahe_run without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array
+ * of MCLAHE_NOALLOC_SCRATCH_BYTES inside the library: every GPU the library
+ * runs on holds its own copy from the first call on it until the process
+ * ends.  The call allocates nothing (no hipMalloc, no hipFree); its first
+ * call on a device looks up that device's copy.  Same kernels, work units
+ * and bits as mclahe_run; the intermediate arrays are not readable.  Every
+ * call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (no clearing is needed: each pass writes what the next reads):
+ * calls that overlap on one GPU (different streams, or threads) race and
+ * must be ordered by the caller.  d_in/d_out as for mclahe_run.
+ * Errors: WORKSPACE if mclahe_workspace_size(plan) exceeds the array (the
+ * call then touches no device), INVALID_VALUE for NULL or misaligned
+ * buffers, HIP if the device or the array's address cannot be queried.     */
+#define MCLAHE_NOALLOC_SCRATCH_BYTES (128ull << 20)
+mclahe_status mclahe_run_noalloc(mclahe_plan_t plan, const void *d_in, void *d_out, void *hip_stream);
+
 /* Workspace bytes for a batched call over n plans (sum of the per-volume
  * workspaces plus the descriptor table).                                    */
 mclahe_status mclahe_batched_workspace_size(int n, const mclahe_plan_t *plans, size_t *bytes);

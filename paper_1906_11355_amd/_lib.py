@@ -19,6 +19,9 @@ LIB_PATH = os.environ.get("MCLAHE_LIB") or os.path.join(_HERE, "libmclahe.so")
 SUCCESS, INVALID_VALUE, NOT_SUPPORTED, OUT_OF_MEMORY, WORKSPACE, HIP_ERROR = range(6)
 U8, U16, F32 = 0, 1, 2
 GLOBAL, KERNEL = 0, 1
+# bytes of the static device scratch behind mclahe_run_noalloc (the header's
+# MCLAHE_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class MclaheError(RuntimeError):
@@ -96,6 +99,7 @@ def _load():
         "mclahe_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_workspace_layout": [P, ctypes.POINTER(Layout)],
         "mclahe_run": [P, P, P, P, ctypes.c_size_t, P],
+        "mclahe_run_noalloc": [P, P, P, P],
         "mclahe_batched_workspace_size": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_batched_workspace_offsets": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_uint64)],
         "mclahe_run_batched": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
@@ -245,6 +249,10 @@ class Plan:
     # ---- device calls (pointers are integers; stream is a hipStream_t) ----
     def run_ptr(self, d_in: int, d_out: int, d_ws: int, ws_bytes: int, stream: int = 0):
         _check(lib.mclahe_run(self._h, d_in, d_out, d_ws, ws_bytes, stream))
+
+    def run_noalloc_ptr(self, d_in: int, d_out: int, stream: int = 0):
+        """mclahe_run on the library's static device scratch (no workspace)."""
+        _check(lib.mclahe_run_noalloc(self._h, d_in, d_out, stream))
 
     def chunked_workspace_size(self, slab_layers: int) -> int:
         n = ctypes.c_size_t()

@@ -1404,6 +1404,52 @@ mclahe_status mclahe_run(mclahe_plan_t p, const void *d_in, void *d_out, void *d
     return run_plain(p, v, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------ no-allocation run --
+// A file-scope device array serves as the workspace of mclahe_run_noalloc.
+// In host code its name is only a stand-in: the device address of each GPU's
+// copy comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is handed to kernels.  Every pass
+// writes all it hands to the next one (range partials, histogram partials,
+// per-kernel arrays), so the array never needs clearing between calls.
+static __device__ __align__(256) unsigned char scratch[MCLAHE_NOALLOC_SCRATCH_BYTES];
+
+static const int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices];   // per device, NULL until set up
+
+static mclahe_status scratch_ptr(char *&ptr)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *a = nullptr;
+        HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        if (!a || ((uintptr_t)a % 256)) return fail(MCLAHE_ERROR_HIP, "scratch array address %p unusable", a);
+        g_scratch_ptr[dev] = (char *)a;
+    }
+    ptr = g_scratch_ptr[dev];
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_noalloc(mclahe_plan_t p, const void *d_in, void *d_out, void *stream)
+{
+    g_err.clear();
+    if (!p) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan is NULL");
+    if (p->total > MCLAHE_NOALLOC_SCRATCH_BYTES)
+        return fail(MCLAHE_ERROR_WORKSPACE, "plan needs %llu workspace bytes, more than the %llu of the static scratch",
+                    (unsigned long long)p->total, (unsigned long long)MCLAHE_NOALLOC_SCRATCH_BYTES);
+    char *ws = nullptr;
+    mclahe_status s = scratch_ptr(ws);
+    if (s) return s;
+    s = check_run_args(p, d_in, d_out, ws, MCLAHE_NOALLOC_SCRATCH_BYTES, p->total);
+    if (s) return s;
+    McVol v;
+    bind(p, v, d_in, d_out, ws);
+    return run_plain(p, v, (hipStream_t)stream);
+}
+
 mclahe_status mclahe_timer_create(mclahe_timer_t *timer, int max_runs)
 {
     if (!timer || max_runs < 1 || max_runs > 100000)

@@ -517,3 +517,24 @@ def test_default_interpolation_groups_keep_256_unit_columns():
     assert p.tuning()["map_group"] == 4
     # per-kernel ranges interpolate one cell at a time
     assert Plan((256, 256, 128), (32, 32, 16), 256, 0.02, "kernel").tuning()["map_group"] == 1
+
+
+def test_noalloc_rejects_plans_beyond_its_scratch_before_any_device_call():
+    """mclahe_run_noalloc refuses a plan whose workspace exceeds the static
+    array, without touching a device (this host has none)."""
+    big = Plan((1024, 1024), (8, 8), 8192, 0.02)
+    assert big.workspace_size() > _lib.NOALLOC_SCRATCH_BYTES
+    with pytest.raises(MclaheError) as e:
+        big.run_noalloc_ptr(16 << 20, 32 << 20, 0)
+    assert e.value.status == _lib.WORKSPACE
+    assert "scratch" in str(e.value)
+    with pytest.raises(MclaheError) as e:
+        _lib._check(_lib.lib.mclahe_run_noalloc(None, None, None, None))
+    assert e.value.status == _lib.INVALID_VALUE
+
+
+def test_noalloc_scratch_size_matches_header():
+    src = open(HEADER).read()
+    m = re.search(r"#define\s+MCLAHE_NOALLOC_SCRATCH_BYTES\s+\((\d+)ull\s*<<\s*(\d+)\)", src)
+    assert m, "MCLAHE_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
