@@ -245,6 +245,41 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans,
                                  void *d_workspace, size_t workspace_bytes,
                                  void *hip_stream);
 
+/* The same batch as ONE persistent launch (after a kernel that clears the
+ * run's counters, both replayed from a hipGraph when the batch repeats):
+ * as many work-groups as fit the chip take tickets in order from one
+ * counter, every ticket one work unit of one pass of one volume, passes in
+ * order (range, histogram, clip/CDF/LUT, interpolation), volumes in batch
+ * order within a pass.  A unit waits, polling an atomic completion counter,
+ * until every unit of its volume's previous pass has finished; tickets come
+ * in dependency order, so the lowest unfinished ticket never waits and the
+ * run cannot deadlock.  Every wait is bounded as well: after max_spins polls
+ * (0 = library default, about a second) it sets one abort word of the run;
+ * every later wait sees the word and ends, every later unit is skipped, and
+ * the kernel drains its tickets and ends normally.  mclahe_persistent_status
+ * reads the word.  Same workspace and bits as mclahe_run_batched.
+ * opts may be NULL.  flags MCLAHE_PERSIST_ABORT_TICKET makes ticket
+ * abort_ticket give up without waiting (to exercise the abort path).       */
+#define MCLAHE_PERSIST_ABORT_TICKET 1u
+typedef struct {
+    uint32_t max_spins;      /* polls of one wait before the run gives up; 0 = default */
+    uint32_t abort_ticket;   /* with MCLAHE_PERSIST_ABORT_TICKET: this ticket gives up */
+    uint32_t flags;
+    uint32_t reserved;
+} mclahe_persistent_opts;
+mclahe_status mclahe_run_batched_persistent(int n, const mclahe_plan_t *plans,
+                                            const void *const *d_in, void *const *d_out,
+                                            void *d_workspace, size_t workspace_bytes,
+                                            const mclahe_persistent_opts *opts, void *hip_stream);
+
+/* After a persistent run on d_workspace (synchronises hip_stream): *aborted
+ * = 0 if every unit ran, else 1 + the ticket whose wait gave up (the
+ * outputs are then incomplete); *tickets (may be NULL) = tickets handed out
+ * (at least the run's total: each work-group takes one more to learn the
+ * queue is empty).                                                          */
+mclahe_status mclahe_persistent_status(int n, const mclahe_plan_t *plans, const void *d_workspace,
+                                       uint32_t *aborted, uint32_t *tickets, void *hip_stream);
+
 /* Bytes of a batch's descriptor table (the head of a batched workspace,
  * before the first volume's own workspace).                                 */
 mclahe_status mclahe_batched_table_size(int n, const mclahe_plan_t *plans, size_t *bytes);
@@ -307,6 +342,29 @@ mclahe_status mclahe_autotune_workspace_size(mclahe_plan_t plan, size_t *bytes);
 mclahe_status mclahe_autotune(mclahe_plan_t plan, const void *d_in, void *d_out,
                               void *d_workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Batch tuning: the work decomposition a plan uses inside batched calls
+ * (mclahe_run_batched and friends), kept apart from the per-volume tuning
+ * above.  Same fields and rules as mclahe_plan_get/set_tuning.              */
+mclahe_status mclahe_plan_get_batch_tuning(mclahe_plan_t plan, mclahe_tuning *tuning);
+mclahe_status mclahe_plan_set_batch_tuning(mclahe_plan_t plan, const mclahe_tuning *tuning);
+
+/* Autotune the batch tuning of n plans together, on the given buffers
+ * (overwritten), by timing whole mclahe_run_batched calls (graph replays):
+ * per class of volumes that run the same kernels, the histogram row split
+ * (default, 2 or 4 times fewer units) with 1 or 2 LDS replicas, then the
+ * interpolation row chunks per unit.  A result is kept only if it is faster
+ * than the default batch tuning when both are timed again, so a tuned batch
+ * is never slower than an untuned one; either way the outputs keep their
+ * bits.  Batched workspace sizes may shrink afterwards (re-query
+ * mclahe_batched_workspace_size).  The workspace must hold
+ * mclahe_autotune_batched_workspace_size() bytes (the batch under default
+ * batch tuning).  Synchronises hip_stream.  Results are cached per problem
+ * class like mclahe_autotune's.                                             */
+mclahe_status mclahe_autotune_batched_workspace_size(int n, const mclahe_plan_t *plans, size_t *bytes);
+mclahe_status mclahe_autotune_batched(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                      void *const *d_out, void *d_workspace, size_t workspace_bytes,
+                                      void *hip_stream);
+
 /* Per-pass timing for benchmarks.  A timer holds HIP events for up to
  * max_runs calls; mclahe_run_timed is mclahe_run that also records an event
  * before each of the four passes and after the last (no synchronisation).
@@ -357,6 +415,23 @@ typedef struct {
     uint64_t count;        /* voxels per volume                               */
 } mclahe_metrics_result;
 mclahe_status mclahe_metrics_workspace_size(int64_t nvox, int n_bins, size_t *bytes);
+
+/* mclahe_run that also computes the contrast metrics (Sec. II; Tables I and
+ * II) of the input x = d_in and the enhanced output y = d_out (its stored
+ * values: codes for u8/u16 output), as mclahe_metrics(d_in, in_dtype, d_out,
+ * out_dtype, ...) defines them, without its separate first pass: the
+ * interpolation units write each unit's minimum, maximum and float64 sum of
+ * x and y as they map; then one pass over both volumes takes the centred
+ * sums and the grey-level histograms (their bins need the ranges first).
+ * Same output bits as mclahe_run.  d_workspace: 256-byte aligned, at least
+ * mclahe_run_metrics_workspace_size() bytes; its head is laid out as
+ * mclahe_workspace_layout() describes.  n_bins, peak, d_result, d_hist as
+ * for mclahe_metrics.  Not in place (d_in != d_out).
+ * Errors: as mclahe_run and mclahe_metrics.                                */
+mclahe_status mclahe_run_metrics_workspace_size(mclahe_plan_t plan, int n_bins, size_t *bytes);
+mclahe_status mclahe_run_metrics(mclahe_plan_t plan, const void *d_in, void *d_out, void *d_workspace,
+                                 size_t workspace_bytes, int n_bins, double peak,
+                                 mclahe_metrics_result *d_result, uint64_t *d_hist, void *hip_stream);
 mclahe_status mclahe_metrics(const void *d_x, mclahe_dtype x_dtype, const void *d_y, mclahe_dtype y_dtype,
                              int64_t nvox, int n_bins, double peak, mclahe_metrics_result *d_result,
                              uint64_t *d_hist, void *d_workspace, size_t workspace_bytes, void *hip_stream);
@@ -400,6 +475,24 @@ mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim,
                               size_t workspace_bytes, void *hip_stream);
 mclahe_status mclahe_median(const void *d_in, mclahe_dtype dtype, int ndim, const int64_t *shape,
                             const int32_t *window, void *d_out, void *hip_stream);
+
+/* Smoothing, then the method: mclahe_gaussian(d_in, in_dtype, plan's shape,
+ * sigma, truncate) into d_smooth (float, the plan's input: the plan must
+ * take f32), then mclahe_run(plan, d_smooth, d_out) -- the paper's pipeline
+ * (Sec. IV: the photoemission volume is smoothed before CLAHE).  Under a
+ * global range computed from the data, when the Gaussian's last pass is the
+ * fused pass over the last two axes, that pass also takes the minimum and
+ * maximum of what it writes, and the method's own range pass (a read of the
+ * whole smoothed volume) is skipped.  Same bits as the two calls in order.
+ * d_workspace: 256-byte aligned, mclahe_run_smoothed_workspace_size()
+ * bytes; its head is laid out as mclahe_workspace_layout() describes.
+ * d_smooth must not overlap d_in, d_out or the workspace.
+ * Errors: as mclahe_gaussian and mclahe_run.                               */
+mclahe_status mclahe_run_smoothed_workspace_size(mclahe_plan_t plan, const double *sigma, double truncate,
+                                                 size_t *bytes);
+mclahe_status mclahe_run_smoothed(mclahe_plan_t plan, const void *d_in, mclahe_dtype in_dtype,
+                                  const double *sigma, double truncate, float *d_smooth, void *d_out,
+                                  void *d_workspace, size_t workspace_bytes, void *hip_stream);
 
 /* Human-readable name of a status code (static storage).                   */
 const char *mclahe_status_string(mclahe_status s);

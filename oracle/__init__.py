@@ -68,6 +68,16 @@ def _load(lib=None):
     return _lib
 
 
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use (from the calling thread)."""
+    return int(ctypes.CDLL(_load()._name).omp_get_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of the oracle's later parallel loops."""
+    ctypes.CDLL(_load()._name).omp_set_num_threads(int(n))
+
+
 def load_library(path: str):
     """Load another build of the oracle source (used by the mutation tests)."""
     return _bind(ctypes.CDLL(path))

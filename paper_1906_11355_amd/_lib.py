@@ -55,6 +55,12 @@ class Variant(ctypes.Structure):
     _fields_ = [("redistribution", ctypes.c_int32), ("rounds", ctypes.c_int32), ("centre", ctypes.c_int32)]
 
 
+class PersistOpts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("max_spins", "abort_ticket", "flags", "reserved")]
+
+
+PERSIST_ABORT_TICKET = 1
+
 REDIST = {"equal": 0, "repeated": 1, "integer": 2}
 CENTRE = {"middle": 0, "half": 1}
 
@@ -113,6 +119,15 @@ def _load():
         "mclahe_run_chunked": [P, P, P, ctypes.c_int, P, ctypes.c_size_t, P],
         "mclahe_autotune_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "mclahe_autotune": [P, P, P, P, ctypes.c_size_t, P],
+        "mclahe_run_batched_persistent": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
+                                          ctypes.c_size_t, ctypes.POINTER(PersistOpts), P],
+        "mclahe_persistent_status": [ctypes.c_int, ctypes.POINTER(P), P, ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.POINTER(ctypes.c_uint32), P],
+        "mclahe_plan_get_batch_tuning": [P, ctypes.POINTER(Tuning)],
+        "mclahe_plan_set_batch_tuning": [P, ctypes.POINTER(Tuning)],
+        "mclahe_autotune_batched_workspace_size": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_autotune_batched": [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
+                                    ctypes.c_size_t, P],
         "mclahe_timer_create": [ctypes.POINTER(P), ctypes.c_int],
         "mclahe_timer_destroy": [P],
         "mclahe_timer_reset": [P],
@@ -126,6 +141,12 @@ def _load():
         "mclahe_median": [P, ctypes.c_int, ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_int32), P, P],
         "mclahe_metrics": [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                            P, P, P, ctypes.c_size_t, P],
+        "mclahe_run_smoothed_workspace_size": [P, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                               ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_run_smoothed": [P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, P, P, P,
+                                ctypes.c_size_t, P],
+        "mclahe_run_metrics_workspace_size": [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+        "mclahe_run_metrics": [P, P, P, P, ctypes.c_size_t, ctypes.c_int, ctypes.c_double, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -219,6 +240,15 @@ class Plan:
         t = Tuning(**{k: int(v) for k, v in kw.items()})
         _check(lib.mclahe_plan_set_tuning(self._h, ctypes.byref(t)))
 
+    def batch_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib.mclahe_plan_get_batch_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_batch_tuning(self, **kw):
+        t = Tuning(**{k: int(v) for k, v in kw.items()})
+        _check(lib.mclahe_plan_set_batch_tuning(self._h, ctypes.byref(t)))
+
     def set_variant(self, redistribution="equal", rounds: int = 1, centre="middle"):
         """Comparison variants of the method (default: the paper's)."""
         v = Variant(REDIST.get(redistribution, redistribution) if isinstance(redistribution, str) else int(redistribution),
@@ -253,6 +283,33 @@ class Plan:
     def run_noalloc_ptr(self, d_in: int, d_out: int, stream: int = 0):
         """mclahe_run on the library's static device scratch (no workspace)."""
         _check(lib.mclahe_run_noalloc(self._h, d_in, d_out, stream))
+
+    def _sigma(self, sigma):
+        if len(sigma) != len(self.shape):
+            raise ValueError("one sigma per axis")
+        return (ctypes.c_double * len(sigma))(*[float(v) for v in sigma])
+
+    def run_smoothed_workspace_size(self, sigma, truncate: float = 4.0) -> int:
+        n = ctypes.c_size_t()
+        _check(lib.mclahe_run_smoothed_workspace_size(self._h, self._sigma(sigma), float(truncate), ctypes.byref(n)))
+        return n.value
+
+    def run_smoothed_ptr(self, d_in: int, in_code: int, sigma, truncate: float, d_smooth: int, d_out: int,
+                         d_ws: int, ws_bytes: int, stream: int = 0):
+        """Gaussian smoothing of d_in into d_smooth (float), then the method on it into d_out."""
+        _check(lib.mclahe_run_smoothed(self._h, d_in, int(in_code), self._sigma(sigma), float(truncate), d_smooth,
+                                       d_out, d_ws, ws_bytes, stream))
+
+    def run_metrics_workspace_size(self, n_bins: int = 256) -> int:
+        n = ctypes.c_size_t()
+        _check(lib.mclahe_run_metrics_workspace_size(self._h, int(n_bins), ctypes.byref(n)))
+        return n.value
+
+    def run_metrics_ptr(self, d_in: int, d_out: int, d_ws: int, ws_bytes: int, n_bins: int, peak: float,
+                        d_result: int, d_hist, stream: int = 0):
+        """mclahe_run plus the contrast metrics of input and output (one MetricsResult at d_result)."""
+        _check(lib.mclahe_run_metrics(self._h, d_in, d_out, d_ws, ws_bytes, int(n_bins), float(peak), d_result,
+                                      d_hist, stream))
 
     def chunked_workspace_size(self, slab_layers: int) -> int:
         n = ctypes.c_size_t()
@@ -316,6 +373,40 @@ def run_batched_ptr(plans, d_ins, d_outs, d_ws: int, ws_bytes: int, stream: int 
     ins = (ctypes.c_void_p * n)(*d_ins)
     outs = (ctypes.c_void_p * n)(*d_outs)
     _check(lib.mclahe_run_batched(n, _plans_array(plans), ins, outs, d_ws, ws_bytes, stream))
+
+
+def autotune_batched_workspace_size(plans) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.mclahe_autotune_batched_workspace_size(len(plans), _plans_array(plans), ctypes.byref(n)))
+    return n.value
+
+
+def autotune_batched_ptr(plans, d_ins, d_outs, d_ws: int, ws_bytes: int, stream: int = 0):
+    """Tune the plans' batch decomposition together on these buffers (overwritten)."""
+    n = len(plans)
+    ins = (ctypes.c_void_p * n)(*d_ins)
+    outs = (ctypes.c_void_p * n)(*d_outs)
+    _check(lib.mclahe_autotune_batched(n, _plans_array(plans), ins, outs, d_ws, ws_bytes, stream))
+
+
+def run_batched_persistent_ptr(plans, d_ins, d_outs, d_ws: int, ws_bytes: int, stream: int = 0,
+                               max_spins: int = 0, abort_ticket=None):
+    """mclahe_run_batched_persistent: the whole batch as one persistent launch."""
+    n = len(plans)
+    ins = (ctypes.c_void_p * n)(*d_ins)
+    outs = (ctypes.c_void_p * n)(*d_outs)
+    o = PersistOpts(int(max_spins), 0 if abort_ticket is None else int(abort_ticket),
+                    0 if abort_ticket is None else PERSIST_ABORT_TICKET, 0)
+    _check(lib.mclahe_run_batched_persistent(n, _plans_array(plans), ins, outs, d_ws, ws_bytes, ctypes.byref(o),
+                                             stream))
+
+
+def persistent_status(plans, d_ws: int, stream: int = 0):
+    """(aborted, tickets) of the last persistent run on d_ws (synchronises the stream)."""
+    a, t = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib.mclahe_persistent_status(len(plans), _plans_array(plans), d_ws, ctypes.byref(a), ctypes.byref(t),
+                                        stream))
+    return a.value, t.value
 
 
 def batched_table_size(plans) -> int:

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libmclahe.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["mclahe.hip", "k_plain_f32.hip", "k_plain_u16.hip", "k_plain_u8.hip", "mc_metrics.hip",
-           "mc_denoise.hip"]
+           "mc_denoise.hip", "k_persist.hip"]
 # measurement tooling, a library of its own (not part of the MCLAHE ABI)
 PROBE_SOURCE = os.path.join(CSRC, "probe", "lds_atomics.hip")
 PROBE_LIB = os.path.join(HERE, "libmclahe_probe.so")

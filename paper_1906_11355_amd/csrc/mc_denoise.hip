@@ -206,6 +206,42 @@ __global__ void __launch_bounds__(kT) k_gauss_rows(const T *in, float *out, int6
     }
 }
 
+// Minimum and maximum over the work-group (kT threads) to dst[0], dst[1].
+__device__ __forceinline__ void block_minmax(float mn, float mx, float *dst)
+{
+    __shared__ float red[2][kT / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o));
+        mx = fmaxf(mx, __shfl_xor(mx, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = mn;
+        red[1][threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kT / 64; ++w) {
+            red[0][0] = fminf(red[0][0], red[0][w]);
+            red[1][0] = fmaxf(red[1][0], red[1][w]);
+        }
+        dst[0] = red[0][0];
+        dst[1] = red[1][0];
+    }
+}
+
+// (min, max) pairs [b n / m, (b + 1) n / m) of src -> pair b of dst, for
+// b < m work-groups.
+__global__ void __launch_bounds__(kT) k_minmax_reduce(const float *src, int64_t n, float *dst, uint32_t m)
+{
+    const int64_t a = n * blockIdx.x / m, b = n * (blockIdx.x + 1) / m;
+    float mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = a + threadIdx.x; i < b; i += kT) {
+        mn = fminf(mn, src[2 * i]);
+        mx = fmaxf(mx, src[2 * i + 1]);
+    }
+    block_minmax(mn, mx, dst + 2 * (int64_t)blockIdx.x);
+}
+
 // The last two axes in one pass (both smoothed, rows of at most kFuseRow
 // samples): a work-group takes T2 consecutive rows along axis D-2 of one
 // outer index, loads them with r2 halo rows on each side (reflected along
@@ -215,11 +251,14 @@ __global__ void __launch_bounds__(kT) k_gauss_rows(const T *in, float *out, int6
 // the result is identical; one round trip through HBM less.
 constexpr int kFuseRow = 512;
 constexpr int kFuseRowTab = kTile / 2 + 2 * kRadiusMax;       // rows a group loads, at most
-constexpr size_t kFuseLds = 65536 - sizeof(int) * kFuseRowTab;  // dynamic LDS of a group
+// dynamic LDS of a group: 64 KiB less the row table and the min/max scratch
+constexpr size_t kFuseLds = 65536 - sizeof(int) * kFuseRowTab - sizeof(float) * 2 * (kT / 64);
 
+// mm: NULL, or room for one (min, max) pair of the outputs per work-group
+// (the global range of the smoothed volume, reduced later).
 template <typename T, int R2, int R3>
 __global__ void __launch_bounds__(kT) k_gauss_last2(const T *in, float *out, int n2, int n3, int r2, int r3,
-                                                   int T2, Weights W2, Weights W3)
+                                                   int T2, Weights W2, Weights W3, float *mm)
 {
     if constexpr (R2 > 0) r2 = R2;
     if constexpr (R3 > 0) r3 = R3;
@@ -314,6 +353,7 @@ __global__ void __launch_bounds__(kT) k_gauss_last2(const T *in, float *out, int
     const int64_t ob = outer * (int64_t)n2 * n3 + (int64_t)q0 * n3;
     t = t00;
     p = p00;
+    float mn = INFINITY, mx = -INFINITY;
     for (int i = threadIdx.x; i < rows * n3; i += kT) {
         const float *src = B + t * rs + p;
         float acc = 0.f;
@@ -324,10 +364,13 @@ __global__ void __launch_bounds__(kT) k_gauss_last2(const T *in, float *out, int
             for (int j = 0; j <= 2 * r3; ++j) acc = __builtin_fmaf(W3.w[j], src[j], acc);
         }
         out[ob + i] = acc;
+        mn = fminf(mn, acc);
+        mx = fmaxf(mx, acc);
         t += dt;
         p += dp;
         if (p >= n3) { p -= n3; ++t; }
     }
+    if (mm) block_minmax(mn, mx, mm + 2 * (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------- strided axes --
@@ -739,7 +782,7 @@ int fuse_rows(int n2, int n3, int r2, int r3)
 
 template <typename T>
 mclahe_status gauss_last2(const T *in, float *out, int64_t nvox, int n2, int n3, int r2, int r3, const Weights &W2,
-                          const Weights &W3, hipStream_t st)
+                          const Weights &W3, hipStream_t st, float *mm)
 {
     const int T2 = fuse_rows(n2, n3, r2, r3);
     const int64_t outer = nvox / ((int64_t)n2 * n3);
@@ -748,12 +791,12 @@ mclahe_status gauss_last2(const T *in, float *out, int64_t nvox, int n2, int n3,
     const size_t lds = sizeof(float) * ((size_t)(T2 + 2 * r2) * n3 + (size_t)T2 * (n3 + 2 * r3));
     const dim3 grid((uint32_t)blocks), blk(kT);
     // common radii as constants; any other pair runs the generic loops
-    if (r2 == 3 && r3 == 3) hipLaunchKernelGGL((k_gauss_last2<T, 3, 3>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
-    else if (r2 == 4 && r3 == 5) hipLaunchKernelGGL((k_gauss_last2<T, 4, 5>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
-    else if (r2 == 3 && r3 == 4) hipLaunchKernelGGL((k_gauss_last2<T, 3, 4>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
-    else if (r2 == 4 && r3 == 4) hipLaunchKernelGGL((k_gauss_last2<T, 4, 4>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
-    else if (r2 == 5 && r3 == 5) hipLaunchKernelGGL((k_gauss_last2<T, 5, 5>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
-    else hipLaunchKernelGGL((k_gauss_last2<T, 0, 0>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3);
+    if (r2 == 3 && r3 == 3) hipLaunchKernelGGL((k_gauss_last2<T, 3, 3>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3, mm);
+    else if (r2 == 4 && r3 == 5) hipLaunchKernelGGL((k_gauss_last2<T, 4, 5>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3, mm);
+    else if (r2 == 3 && r3 == 4) hipLaunchKernelGGL((k_gauss_last2<T, 3, 4>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3, mm);
+    else if (r2 == 4 && r3 == 4) hipLaunchKernelGGL((k_gauss_last2<T, 4, 4>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3, mm);
+    else if (r2 == 5 && r3 == 5) hipLaunchKernelGGL((k_gauss_last2<T, 5, 5>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3, mm);
+    else hipLaunchKernelGGL((k_gauss_last2<T, 0, 0>), grid, blk, lds, st, in, out, n2, n3, r2, r3, T2, W2, W3, mm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mc_fail(MCLAHE_ERROR_HIP, "gaussian pass launch failed: %s", hipGetErrorString(e));
     return MCLAHE_SUCCESS;
@@ -806,25 +849,48 @@ mclahe_status median_launch(const void *in, void *out, const MedGeom &g, hipStre
 
 }  // namespace
 
-extern "C" {
-
-mclahe_status mclahe_gaussian_workspace_size(int ndim, const int64_t *shape, const double *sigma, size_t *bytes)
+// Axes a Gaussian call smooths, and whether its last two go in one fused
+// pass (both smoothed, short rows, one row group within the LDS budget).
+static void gauss_axes(int ndim, const int64_t *shape, const double *sigma, double truncate, std::vector<int> &axes,
+                       bool &fuse)
 {
-    mc_clear_error();
-    int64_t nvox;
-    mclahe_status s = check_shape(ndim, shape, nvox);
-    if (s) return s;
-    if (!sigma || !bytes) return mc_fail(MCLAHE_ERROR_INVALID_VALUE, "sigma and bytes must not be NULL");
-    int passes = 0;
-    for (int i = 0; i < ndim; ++i) passes += sigma[i] > 0.0;
-    // (a fused last-two-axes pass needs no more: the bound stays one volume)
-    *bytes = passes >= 2 ? ((sizeof(float) * nvox + 255) & ~size_t(255)) : 0;
-    return MCLAHE_SUCCESS;
+    axes.clear();
+    for (int i = 0; i < ndim; ++i)
+        if (sigma[i] > 0.0) axes.push_back(i);
+    const int P = (int)axes.size();
+    fuse = P >= 2 && axes[P - 1] == ndim - 1 && axes[P - 2] == ndim - 2 && shape[ndim - 1] <= kFuseRow;
+    if (fuse) {
+        const int64_t n3 = shape[ndim - 1];
+        const int r2 = gauss_radius(sigma[ndim - 2], truncate), r3 = gauss_radius(sigma[ndim - 1], truncate);
+        fuse = sizeof(float) * ((1 + 2 * r2) * n3 + (n3 + 2 * r3)) <= kFuseLds &&
+               shape[ndim - 2] * n3 < (1LL << 31);       // row offsets in 32 bits
+    }
 }
 
-mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim, const int64_t *shape,
-                              const double *sigma, double truncate, float *d_out, void *d_workspace,
-                              size_t workspace_bytes, void *hip_stream)
+int64_t mc_gaussian_mm_parts(int ndim, const int64_t *shape, const double *sigma, double truncate)
+{
+    std::vector<int> axes;
+    bool fuse = false;
+    gauss_axes(ndim, shape, sigma, truncate, axes, fuse);
+    if (!fuse) return 0;
+    int64_t nvox = 1;
+    for (int i = 0; i < ndim; ++i) nvox *= shape[i];
+    const int n2 = (int)shape[ndim - 2], n3 = (int)shape[ndim - 1];
+    const int T2 = fuse_rows(n2, n3, gauss_radius(sigma[ndim - 2], truncate), gauss_radius(sigma[ndim - 1], truncate));
+    return nvox / ((int64_t)n2 * n3) * ((n2 + T2 - 1) / T2);
+}
+
+mclahe_status mc_minmax_reduce(const float *src, int64_t n, float *dst, uint32_t m, hipStream_t st)
+{
+    if (m == 0) return MCLAHE_SUCCESS;
+    hipLaunchKernelGGL(k_minmax_reduce, dim3(m), dim3(kT), 0, st, src, n, dst, m);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MCLAHE_SUCCESS : mc_fail(MCLAHE_ERROR_HIP, "launch failed: %s", hipGetErrorString(e));
+}
+
+mclahe_status mc_gaussian_run(const void *d_in, int in_dtype, int ndim, const int64_t *shape, const double *sigma,
+                              double truncate, float *d_out, void *d_workspace, size_t workspace_bytes, float *mm,
+                              hipStream_t st)
 {
     size_t need = 0;
     mclahe_status s = mclahe_gaussian_workspace_size(ndim, shape, sigma, &need);
@@ -848,10 +914,9 @@ mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim,
         return mc_fail(MCLAHE_ERROR_INVALID_VALUE, "input and output must not overlap");
     if (need && (!d_workspace || ((uintptr_t)d_workspace & 255) || workspace_bytes < need))
         return mc_fail(MCLAHE_ERROR_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned", need);
-    hipStream_t st = (hipStream_t)hip_stream;
     std::vector<int> axes;
-    for (int i = 0; i < ndim; ++i)
-        if (sigma[i] > 0.0) axes.push_back(i);
+    bool fuse = false;
+    gauss_axes(ndim, shape, sigma, truncate, axes, fuse);
     const int P = (int)axes.size();
     if (P == 0) {
         const uint32_t blocks = (uint32_t)std::min<int64_t>(4096, (nvox + kT - 1) / kT);
@@ -862,14 +927,8 @@ mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim,
         return e == hipSuccess ? MCLAHE_SUCCESS : mc_fail(MCLAHE_ERROR_HIP, "launch failed: %s", hipGetErrorString(e));
     }
     // launches: one per smoothed axis, except that the last two axes go in
-    // one fused pass when both are smoothed and the rows are short
-    bool fuse = P >= 2 && axes[P - 1] == ndim - 1 && axes[P - 2] == ndim - 2 && shape[ndim - 1] <= kFuseRow;
-    if (fuse) {   // one row group must fit the LDS budget
-        const int64_t n3 = shape[ndim - 1];
-        const int r2 = gauss_radius(sigma[ndim - 2], truncate), r3 = gauss_radius(sigma[ndim - 1], truncate);
-        fuse = sizeof(float) * ((1 + 2 * r2) * n3 + (n3 + 2 * r3)) <= kFuseLds &&
-               shape[ndim - 2] * n3 < (1LL << 31);       // row offsets in 32 bits
-    }
+    // one fused pass when both are smoothed and the rows are short (that
+    // pass also writes the min/max pairs when mm is given)
     const int L = fuse ? P - 1 : P;
     float *tmp = (float *)d_workspace;
     const float *src = nullptr;
@@ -885,11 +944,11 @@ mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim,
             gauss_weights(sigma[ndim - 1], truncate, W3, r3);
             const int n2 = (int)shape[ndim - 2], n3 = (int)shape[ndim - 1];
             if (k == 0) {
-                if (in_dtype == MCLAHE_U8) s = gauss_last2<uint8_t>((const uint8_t *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st);
-                else if (in_dtype == MCLAHE_U16) s = gauss_last2<uint16_t>((const uint16_t *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st);
-                else s = gauss_last2<float>((const float *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st);
+                if (in_dtype == MCLAHE_U8) s = gauss_last2<uint8_t>((const uint8_t *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st, mm);
+                else if (in_dtype == MCLAHE_U16) s = gauss_last2<uint16_t>((const uint16_t *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st, mm);
+                else s = gauss_last2<float>((const float *)d_in, dst, nvox, n2, n3, r, r3, W, W3, st, mm);
             } else {
-                s = gauss_last2<float>(src, dst, nvox, n2, n3, r, r3, W, W3, st);
+                s = gauss_last2<float>(src, dst, nvox, n2, n3, r, r3, W, W3, st, mm);
             }
         } else {
             int64_t S = 1;
@@ -906,6 +965,30 @@ mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim,
         src = dst;
     }
     return MCLAHE_SUCCESS;
+}
+
+extern "C" {
+
+mclahe_status mclahe_gaussian_workspace_size(int ndim, const int64_t *shape, const double *sigma, size_t *bytes)
+{
+    mc_clear_error();
+    int64_t nvox;
+    mclahe_status s = check_shape(ndim, shape, nvox);
+    if (s) return s;
+    if (!sigma || !bytes) return mc_fail(MCLAHE_ERROR_INVALID_VALUE, "sigma and bytes must not be NULL");
+    int passes = 0;
+    for (int i = 0; i < ndim; ++i) passes += sigma[i] > 0.0;
+    // (a fused last-two-axes pass needs no more: the bound stays one volume)
+    *bytes = passes >= 2 ? ((sizeof(float) * nvox + 255) & ~size_t(255)) : 0;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_gaussian(const void *d_in, mclahe_dtype in_dtype, int ndim, const int64_t *shape,
+                              const double *sigma, double truncate, float *d_out, void *d_workspace,
+                              size_t workspace_bytes, void *hip_stream)
+{
+    return mc_gaussian_run(d_in, in_dtype, ndim, shape, sigma, truncate, d_out, d_workspace, workspace_bytes,
+                           nullptr, (hipStream_t)hip_stream);
 }
 
 mclahe_status mclahe_median(const void *d_in, mclahe_dtype dtype, int ndim, const int64_t *shape,

@@ -116,6 +116,15 @@ MC_HD constexpr int mc_vec_elems(int esize) { return esize == 1 ? 8 : 16 / esize
 // Work-group size of the LDS-staged map kernels.
 MC_HD constexpr int mc_map_threads(bool ahr) { return ahr ? MC_T : MC_MAP_T; }
 
+// Partial statistics of one work unit for the contrast metrics: minimum,
+// maximum and float64 sum of the input ([0]) and of the stored output ([1])
+// over the unit's voxels (the same record the metrics' own range pass
+// writes per work-group).
+struct McMetPart {
+    float mn[2], mx[2];
+    double sum[2];
+};
+
 // Everything the kernels need about one volume.
 struct McVol {
     // ---- problem -----------------------------------------------------------
@@ -160,7 +169,10 @@ struct McVol {
     float *lut;               // [nker][nb]
     float *range;             // GHR: [2]; AHR: [nker][2]
     float *scale;             // GHR: [1]; AHR: [nker]
+    McMetPart *met;           // contrast metrics: [n_map_wu] partials of the
+                              // interpolation units (NULL: not computed)
 };
+
 
 // Batched descriptor table (device memory, uploaded per call): a header, one
 // record per batched launch, the launches' index arrays, then the volume
@@ -168,7 +180,9 @@ struct McVol {
 // class (the template instance the per-volume path would launch).
 #define MC_PHASES 4
 struct McBatchHdr {
-    uint32_t nvol, nlaunch, pad_[2];
+    uint32_t nvol, nlaunch;
+    uint32_t o_persist;   // byte offset of the persistent launch's table (McPersistHdr)
+    uint32_t pad_;
 };
 struct McLaunchRec {
     uint32_t phase;    // 0 range, 1 histogram, 2 clip/CDF, 3 map

@@ -56,7 +56,10 @@ __device__ __forceinline__ int f2o(float f)
 }
 __device__ __forceinline__ float o2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
 
-// V consecutive input elements (16-byte aligned when V > 1) as floats.
+// V consecutive input elements as floats, with one 16- or 8-byte load.  A
+// chunk starts at any element of a row (the HSA runtime runs the GPU in
+// unaligned-access mode, so wide loads need no alignment); the last chunk
+// of a row whose length is not a multiple of V is its last V elements.
 template <typename Tin, int V>
 __device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)[V])
 {
@@ -105,17 +108,94 @@ __device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
     return ((const float *)in)[i];
 }
 
+// The value an output element holds, as a float: y itself, or its integer
+// code min(M, floor(y * M + 0.5)) for 8- and 16-bit output.
+__device__ __forceinline__ float out_value(int dt, float y)
+{
+    if (dt == MC_F32) return y;
+    const float M = dt == MC_U8 ? 255.0f : 65535.0f;
+    const float q = floorf(y * M + 0.5f);
+    return fminf(fmaxf(q, 0.0f), M);
+}
+
 // Quantised or float store of one output value.
 __device__ __forceinline__ void store_elem(void *out, int dt, int64_t i, float y)
 {
-    if (dt == MC_F32) {
-        ((float *)out)[i] = y;
-    } else {
-        const float M = dt == MC_U8 ? 255.0f : 65535.0f;
-        float q = floorf(y * M + 0.5f);
-        q = fminf(fmaxf(q, 0.0f), M);
-        if (dt == MC_U8) ((uint8_t *)out)[i] = (uint8_t)q;
-        else ((uint16_t *)out)[i] = (uint16_t)q;
+    const float q = out_value(dt, y);
+    if (dt == MC_F32) ((float *)out)[i] = q;
+    else if (dt == MC_U8) ((uint8_t *)out)[i] = (uint8_t)q;
+    else ((uint16_t *)out)[i] = (uint16_t)q;
+}
+
+// Contrast-metric accumulators of one thread: minimum, maximum and float64
+// sum of the input and of the stored output over the voxels it maps.
+struct MetAcc {
+    float mn[2], mx[2];
+    double sum[2];
+    __device__ __forceinline__ void init()
+    {
+        mn[0] = mn[1] = INFINITY;
+        mx[0] = mx[1] = -INFINITY;
+        sum[0] = sum[1] = 0.0;
+    }
+    __device__ __forceinline__ void add(float x, float y)
+    {
+        mn[0] = fminf(mn[0], x);
+        mx[0] = fmaxf(mx[0], x);
+        sum[0] += (double)x;
+        mn[1] = fminf(mn[1], y);
+        mx[1] = fmaxf(mx[1], y);
+        sum[1] += (double)y;
+    }
+};
+
+// Work-group reduction of the accumulators (NT threads; fixed order, so the
+// partial is the same on every run) into the unit's record.  smem: at least
+// 6 * 8 * (NT / 64) bytes, free for reuse (the caller has synchronised).
+template <int NT>
+__device__ __forceinline__ void met_flush(const MetAcc &a, char *smem, McMetPart *dst)
+{
+    constexpr int NW = NT / 64;
+    float mn0 = a.mn[0], mx0 = a.mx[0], mn1 = a.mn[1], mx1 = a.mx[1];
+    double s0 = a.sum[0], s1 = a.sum[1];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn0 = fminf(mn0, __shfl_xor(mn0, o));
+        mx0 = fmaxf(mx0, __shfl_xor(mx0, o));
+        mn1 = fminf(mn1, __shfl_xor(mn1, o));
+        mx1 = fmaxf(mx1, __shfl_xor(mx1, o));
+        s0 += __shfl_xor(s0, o);
+        s1 += __shfl_xor(s1, o);
+    }
+    float *f = (float *)smem;                  // [4][NW]
+    double *g = (double *)(smem + 16 * NW);    // [2][NW]
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        f[w] = mn0;
+        f[NW + w] = mx0;
+        f[2 * NW + w] = mn1;
+        f[3 * NW + w] = mx1;
+        g[w] = s0;
+        g[NW + w] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        McMetPart r;
+        r.mn[0] = f[0];
+        r.mx[0] = f[NW];
+        r.mn[1] = f[2 * NW];
+        r.mx[1] = f[3 * NW];
+        r.sum[0] = g[0];
+        r.sum[1] = g[NW];
+        for (int q = 1; q < NW; ++q) {
+            r.mn[0] = fminf(r.mn[0], f[q]);
+            r.mx[0] = fmaxf(r.mx[0], f[NW + q]);
+            r.mn[1] = fminf(r.mn[1], f[2 * NW + q]);
+            r.mx[1] = fmaxf(r.mx[1], f[3 * NW + q]);
+            r.sum[0] += g[q];
+            r.sum[1] += g[NW + q];
+        }
+        *dst = r;
     }
 }
 
@@ -598,8 +678,12 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int tch = cpr > 0 ? (int)threadIdx.x % cpr : 0;
     const int trow = cpr > 0 ? (int)threadIdx.x / cpr : MC_T;
     const bool tact = trow < rpi && r0 + trow < r1;
+    // a chunk that would run past the row end (rows not a multiple of V) is
+    // read as the row's last V elements instead; the ones it shares with the
+    // previous chunk are skipped
+    const int x0 = (c_lo + tch) * V, xl = mc_min(x0, d.ax[D - 1].s - V);
     Memb<V> m;
-    build_memb<V>(d, kA, kB, xs, xe, (c_lo + tch) * V, m);
+    build_memb<V>(d, kA, kB, mc_max(xs, x0), xe, xl, m);
     float lo1[V], sc1[V], mn[V], mx[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) {
@@ -622,7 +706,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         int r = (int)(rstart - o * rs.in_len);
         const int64_t so = rpi / rs.in_len;
         const int sr = (int)(rpi - so * rs.in_len);
-        const int64_t xoff = (int64_t)(c_lo + tch) * V;
+        const int64_t xoff = xl;
         // U rows per step.  Software pipelined: the loads of the next U rows
         // are issued before the current U rows are binned, so every wave
         // keeps up to 2U wide loads in flight while it works.
@@ -934,10 +1018,11 @@ struct MapOTab {
     float coef[NOH];
 };
 
-template <typename Tin, int D, bool AHR, int V>
+// NT: work-group size (the per-pass kernels use mc_map_threads(AHR); the
+// persistent batched kernel runs every unit with MC_T threads)
+template <typename Tin, int D, bool AHR, int V, bool MET, int NT>
 __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
 {
-    constexpr int NT = mc_map_threads(AHR);   // work-group size
     constexpr int NC = 1 << D;                 // corners
     constexpr int NO = 1 << (D - 1);           // outer corners
     using OT = MapOTab<D>;
@@ -1023,14 +1108,26 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
 
     // the LUTs (and AHR ranges) staged above are published by the first
     // chunk's barrier below
-    if (xe <= xs) return;   // an empty split part (uniform over the work-group)
+    if (xe <= xs) {         // an empty split part (uniform over the work-group)
+        if constexpr (MET) {
+            if (threadIdx.x == 0) d.met[wu] = McMetPart{{INFINITY, INFINITY}, {-INFINITY, -INFINITY}, {0.0, 0.0}};
+        }
+        return;
+    }
+    MetAcc macc;
+    if constexpr (MET) macc.init();
     // thread mapping along the last axis (a split cell part may be empty)
     const int c_lo = xs / V, c_hi = (xe + V - 1) / V;
     const int cpr = c_hi - c_lo;
     const int rpi = NT / cpr;
     const int tch = threadIdx.x % cpr, trow = threadIdx.x / cpr;
     const bool tact = trow < rpi;
-    const int64_t xoff = (int64_t)(c_lo + tch) * V;
+    // a chunk that would run past the row end (rows not a multiple of V) is
+    // read as the row's last V elements instead; the ones it shares with the
+    // previous chunk are skipped
+    const int x0 = (c_lo + tch) * V;
+    const int64_t xoff = mc_min(x0, al.s - V);
+    const int xvs = mc_max(xs, x0);   // first position this thread maps
     int lbase[V];      // LDS offset of the voxel's last-axis kernel pair
     float wl[V];
     bool val[V];
@@ -1038,7 +1135,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         const int x = (int)xoff + e;
-        val[e] = x >= xs && x < xe;
+        val[e] = x >= xvs && x < xe;
         allv = allv && val[e];
         int c = cA;
         if (val[e]) {
@@ -1203,22 +1300,31 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                     for (int e = 0; e < V; ++e)
                         if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
                 }
+                if constexpr (MET) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (val[e]) macc.add(fu[u][e], out_value(d.out_dt, y[e]));
+                }
             }
         }
     }
+    if constexpr (MET) {
+        __syncthreads();   // every reader of the staged tables is done
+        met_flush<NT>(macc, smem, d.met + wu);
+    }
 }
 
-template <typename Tin, int D, bool AHR>
+template <typename Tin, int D, bool AHR, bool MET = false, int NT = mc_map_threads(AHR)>
 __device__ void map_unit(const McVol &d, uint32_t wu, char *smem)
 {
     constexpr int VM = mc_vec_elems((int)sizeof(Tin));
-    if (d.vec == VM) map_unit_v<Tin, D, AHR, VM>(d, wu, smem);
-    else map_unit_v<Tin, D, AHR, 1>(d, wu, smem);
+    if (d.vec == VM) map_unit_v<Tin, D, AHR, VM, MET, NT>(d, wu, smem);
+    else map_unit_v<Tin, D, AHR, 1, MET, NT>(d, wu, smem);
 }
 
 // Generic interpolation (any D up to 8, or LUTs too large for LDS): one cell
 // per unit, LUTs read from global memory, corners summed in index order.
-template <typename Tin, bool AHR>
+template <typename Tin, bool AHR, bool MET = false>
 __device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
 {
     const int D = d.D, nb = d.nb;
@@ -1260,6 +1366,8 @@ __device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
     const int64_t nel = (r1 - r0) * xl;
     const float nbf = (float)nb;
     const int nbm1 = nb - 1;
+    MetAcc macc;
+    if constexpr (MET) macc.init();
     for (int64_t e = threadIdx.x; e < nel; e += MC_T) {
         const int64_t row = r0 + e / xl;
         const int x = xs + (int)(e - (row - r0) * xl);
@@ -1300,7 +1408,9 @@ __device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
             y = __fmaf_rn(coef, d.lut[kid * nb + bin_of(v, lo, sc, nbf, nbm1)], y);
         }
         store_elem(d.out, d.out_dt, off, y);
+        if constexpr (MET) macc.add(v, out_value(d.out_dt, y));
     }
+    if constexpr (MET) met_flush<MC_T>(macc, smem, d.met + wu);
 }
 
 }  // namespace mc

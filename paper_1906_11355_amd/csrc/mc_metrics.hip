@@ -39,10 +39,9 @@ constexpr int kMaxBins = 8192;   // two LDS histograms of this many u32: 64 KiB
 constexpr int kMaxCopies = 4;    // lane-interleaved copies of each bin
 constexpr size_t kCopyLds = 32 * 1024;   // LDS the copies may take
 
-struct RangePart {      // one per work-group of the range pass
-    float mn[2], mx[2];
-    double sum[2];
-};
+// One per work-group of the range pass (or per interpolation unit of a
+// CLAHE run that computes the metrics on the way): min, max, float64 sum.
+using RangePart = McMetPart;
 struct Stats {          // per volume, written by the stats step
     float lo[2], hi[2], scale[2];
     int32_t pad_;
@@ -381,10 +380,12 @@ MetLayout met_layout(int64_t nvox, int nb)
     return L;
 }
 
+// parts: NULL, or the nparts min/max/sum records of x and y already written
+// by the interpolation units of a CLAHE run (then the range pass is skipped).
 template <typename TX, typename TY, bool VEC>
 mclahe_status launch_passes(const void *x, const void *y, int64_t nvox, int nb, double peak,
                             mclahe_metrics_result *res, unsigned long long *hist_out, char *ws,
-                            hipStream_t st)
+                            hipStream_t st, const RangePart *parts = nullptr, int nparts = 0)
 {
     constexpr bool HY = !std::is_same<TY, None>::value;
     const int nv = HY ? 2 : 1, g = met_groups(nvox);
@@ -393,9 +394,13 @@ mclahe_status launch_passes(const void *x, const void *y, int64_t nvox, int nb, 
     RangePart *rp = (RangePart *)(ws + L.rpart);
     AccPart *ap = (AccPart *)(ws + L.apart);
     unsigned long long *h = (unsigned long long *)(ws + L.hist);
-    hipLaunchKernelGGL((k_met_range<TX, TY, VEC>), dim3(g), dim3(kT), 0, st, (const TX *)x, (const TY *)y, nvox,
-                       rp);
-    hipLaunchKernelGGL(k_met_stats, dim3(1), dim3(kT), 0, st, rp, g, nv, nvox, nb, sp, h);
+    if (parts) {
+        hipLaunchKernelGGL(k_met_stats, dim3(1), dim3(kT), 0, st, parts, nparts, nv, nvox, nb, sp, h);
+    } else {
+        hipLaunchKernelGGL((k_met_range<TX, TY, VEC>), dim3(g), dim3(kT), 0, st, (const TX *)x, (const TY *)y,
+                           nvox, rp);
+        hipLaunchKernelGGL(k_met_stats, dim3(1), dim3(kT), 0, st, rp, g, nv, nvox, nb, sp, h);
+    }
     int rs = 0;   // copies per bin: as many as fit the LDS budget, at most 4
     while ((2 << rs) <= kMaxCopies && sizeof(uint32_t) * nv * nb * (2 << rs) <= kCopyLds) ++rs;
     const size_t lds = std::max(sizeof(uint32_t) * nv * nb * (1 << rs), 4 * sizeof(double));
@@ -410,7 +415,8 @@ mclahe_status launch_passes(const void *x, const void *y, int64_t nvox, int nb, 
 
 template <typename TX, typename TY>
 mclahe_status pick_vec(const void *x, const void *y, int64_t nvox, int nb, double peak,
-                       mclahe_metrics_result *res, unsigned long long *hist_out, char *ws, hipStream_t st)
+                       mclahe_metrics_result *res, unsigned long long *hist_out, char *ws, hipStream_t st,
+                       const RangePart *parts = nullptr, int nparts = 0)
 {
     // vector loads need both bases aligned to one chunk's access width
     auto aligned = [](const void *p, size_t es) {
@@ -419,8 +425,20 @@ mclahe_status pick_vec(const void *x, const void *y, int64_t nvox, int nb, doubl
     };
     bool vec = aligned(x, sizeof(TX));
     if constexpr (!std::is_same<TY, None>::value) vec = vec && aligned(y, sizeof(TY));
-    return vec ? launch_passes<TX, TY, true>(x, y, nvox, nb, peak, res, hist_out, ws, st)
-               : launch_passes<TX, TY, false>(x, y, nvox, nb, peak, res, hist_out, ws, st);
+    return vec ? launch_passes<TX, TY, true>(x, y, nvox, nb, peak, res, hist_out, ws, st, parts, nparts)
+               : launch_passes<TX, TY, false>(x, y, nvox, nb, peak, res, hist_out, ws, st, parts, nparts);
+}
+
+template <typename TX>
+mclahe_status pick_y_parts(const void *x, const void *y, int ydt, int64_t nvox, int nb, double peak,
+                           mclahe_metrics_result *res, unsigned long long *hist_out, char *ws, hipStream_t st,
+                           const RangePart *parts, int nparts)
+{
+    switch (ydt) {
+    case MCLAHE_U8: return pick_vec<TX, uint8_t>(x, y, nvox, nb, peak, res, hist_out, ws, st, parts, nparts);
+    case MCLAHE_U16: return pick_vec<TX, uint16_t>(x, y, nvox, nb, peak, res, hist_out, ws, st, parts, nparts);
+    default: return pick_vec<TX, float>(x, y, nvox, nb, peak, res, hist_out, ws, st, parts, nparts);
+    }
 }
 
 template <typename TX>
@@ -438,6 +456,24 @@ mclahe_status pick_y(const void *x, const void *y, int ydt, int64_t nvox, int nb
 bool valid_dt(int dt) { return dt == MCLAHE_U8 || dt == MCLAHE_U16 || dt == MCLAHE_F32; }
 
 }  // namespace
+
+size_t mc_metrics_tail_ws(int64_t nvox, int n_bins, int nparts)
+{
+    (void)nparts;   // the records stay where the interpolation units wrote them
+    return met_layout(nvox, n_bins).total;
+}
+
+mclahe_status mc_metrics_tail(const void *x, int x_dt, const void *y, int y_dt, int64_t nvox, int n_bins,
+                              double peak, const McMetPart *parts, int nparts, mclahe_metrics_result *res,
+                              uint64_t *hist_out, char *ws, hipStream_t st)
+{
+    unsigned long long *ho = (unsigned long long *)hist_out;
+    switch (x_dt) {
+    case MCLAHE_U8: return pick_y_parts<uint8_t>(x, y, y_dt, nvox, n_bins, peak, res, ho, ws, st, parts, nparts);
+    case MCLAHE_U16: return pick_y_parts<uint16_t>(x, y, y_dt, nvox, n_bins, peak, res, ho, ws, st, parts, nparts);
+    default: return pick_y_parts<float>(x, y, y_dt, nvox, n_bins, peak, res, ho, ws, st, parts, nparts);
+    }
+}
 
 extern "C" {
 

@@ -76,6 +76,39 @@ __global__ __launch_bounds__(MC_T) void k_map_generic_b(McBatchSrc s)
     mc::map_unit_generic<Tin, AHR>(d, u, smem);
 }
 
+// Interpolation with the contrast-metric epilogue (per-volume runs only):
+// the same unit function, which also writes each unit's input and output
+// statistics.
+template <typename Tin, int D, bool AHR>
+__global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map_m(McVol d)
+{
+    extern __shared__ __align__(16) char smem[];
+    mc::map_unit<Tin, D, AHR, true>(d, blockIdx.x, smem);
+}
+template <typename Tin, bool AHR>
+__global__ __launch_bounds__(MC_T) void k_map_generic_m(McVol d)
+{
+    extern __shared__ __align__(16) char smem[];
+    mc::map_unit_generic<Tin, AHR, true>(d, blockIdx.x, smem);
+}
+
+template <typename Tin, bool AHR>
+static KFn pick_map_met_t(int D, int path)
+{
+    if (path) return (KFn)k_map_generic_m<Tin, AHR>;
+    switch (D) {
+    case 1: return (KFn)k_map_m<Tin, 1, AHR>;
+    case 2: return (KFn)k_map_m<Tin, 2, AHR>;
+    case 3: return (KFn)k_map_m<Tin, 3, AHR>;
+    default: return (KFn)k_map_m<Tin, 4, AHR>;
+    }
+}
+
+template <typename Tin>
+static KFn pick_map_met_t2(int D, bool ahr, int path)
+{
+    return ahr ? pick_map_met_t<Tin, true>(D, path) : pick_map_met_t<Tin, false>(D, path);
+}
 
 template <typename Tin, bool AHR, bool RO, int PEEL>
 static KPair hist_pair() { return KPair{(KFn)k_hist<Tin, AHR, RO, PEEL>, (KFnB)k_hist_b<Tin, AHR, RO, PEEL>, MC_T}; }

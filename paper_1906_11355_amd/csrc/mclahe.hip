@@ -25,6 +25,7 @@
 #include "../../include/mclahe.h"
 #include "mc_desc.h"
 #include "mc_kernels.h"
+#include "mc_persist.h"
 
 // ------------------------------------------------------------------ errors --
 static thread_local std::string g_err;
@@ -108,6 +109,12 @@ static int64_t clip_count(double clip, int64_t K)
 // Batched launches fill the chip with the units of many volumes, so they take
 // coarser units.
 static const int64_t kUnitVoxPlain = 16384, kUnitVoxBatch = 65536;
+// Voxels per interpolation unit a batched volume aims at under a global range
+// (a unit then stages its LUTs for about as many rows as at the 4D headline)
+static const int64_t kMapUnitVoxBatch = 262144;
+// Polls of one wait of the persistent launch before the run gives up (each
+// poll an atomic and a short sleep: on the order of a second in all)
+static const uint32_t kPersistSpins = 1u << 20;
 // unit columns the plain interpolation pass keeps at least (one per CU)
 static const int64_t kMinMapCols = 256;
 
@@ -151,9 +158,11 @@ static int seg_chunks(int xs, int xe, int V) { return (xe + V - 1) / V - xs / V;
 
 // Derive a work decomposition from tuning t, with default work units of at
 // least unit_vox voxels, for vector loads (vector: chunks of mc_vec_elems
-// elements when the last axis is a multiple of it) or scalar loads.
+// elements when the last axis holds at least one) or scalar loads.  Under
+// a global range, interpolation units run row chunks on one staging of
+// their LUTs: by default as many as leave map_units units for the volume.
 static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t, int64_t unit_vox,
-                                 int64_t min_map_cols, bool vector, McVol &v)
+                                 int64_t min_map_cols, int64_t map_units, bool vector, McVol &v)
 {
     memset(&v, 0, sizeof v);
     const int D = p->D;
@@ -177,7 +186,10 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
     v.nker = p->nker;
     const McAxis &al = p->ax[D - 1];
     const int vmax = mc_vec_elems((int)esize(p->in_dt));
-    const int V = (vector && al.s % vmax == 0) ? vmax : 1;
+    // chunks start at any element of a row (global memory takes unaligned
+    // wide loads); the chunk that would run past a row's end is read as the
+    // row's last vmax elements, so a row needs at least one whole chunk
+    const int V = (vector && al.s >= vmax) ? vmax : 1;
     v.vec = V;
     const int maxchunks = MC_T - 1;
 
@@ -372,13 +384,15 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
     mcr = std::min<int64_t>(mcr, std::max<int64_t>(rmax_m, crmin_m));
     v.mCr = (int)mcr;
     // row chunks per unit: each unit stages its LUTs once for mK chunks.
-    // Default: as many as keep >= 1024 units (four per CU).
+    // Default: as many as keep >= map_units units (1024 for one volume, four
+    // per CU; fewer for a volume of a batch, whose units share the chip with
+    // the others' and would otherwise stage their LUTs for few rows)
     int mk = 1;
     if (fast && p->mode == MC_GHR) {
         if (t.map_unit_chunks > 0) {
             mk = t.map_unit_chunks;
         } else {
-            const int64_t want_u = std::max<int64_t>(1, (1024 + v.mCols * v.mS - 1) / (v.mCols * v.mS));
+            const int64_t want_u = std::max<int64_t>(1, (map_units + v.mCols * v.mS - 1) / (v.mCols * v.mS));
             mk = (int)((mcr + want_u - 1) / want_u);
         }
         mk = std::max(1, std::min(mk, v.mCr));
@@ -418,10 +432,11 @@ static size_t pass_lds(const mclahe_plan_s *p, const McVol &v, int ph)
 static mclahe_status derive(mclahe_plan_s *p)
 {
     mclahe_status s;
-    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, true, p->bv))) return s;
-    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, false, p->bv1))) return s;
-    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, true, p->v))) return s;
-    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, false, p->v1))) return s;
+    const int64_t bmu = std::max<int64_t>(1, p->nvox / kMapUnitVoxBatch);
+    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, bmu, true, p->bv))) return s;
+    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, bmu, false, p->bv1))) return s;
+    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, 1024, true, p->v))) return s;
+    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, 1024, false, p->v1))) return s;
     uint64_t pw = 0, rf = 0;
     for (const McVol *d : {&p->v, &p->v1, &p->bv, &p->bv1}) {
         pw = std::max(pw, part_words(*d));
@@ -446,10 +461,15 @@ static mclahe_status derive(mclahe_plan_s *p)
     return MCLAHE_SUCCESS;
 }
 
-// Vector loads and stores need both buffers on 16-byte boundaries.
-static bool vec_aligned(const void *in, const void *out)
+// Wide loads and stores work at any element address (the HSA runtime runs
+// the GPU in unaligned-access mode), so the vector decomposition serves any
+// buffers; the scalar one remains for rows shorter than one chunk.
+static bool vec_aligned(const mclahe_plan_s *p, const void *in, const void *out)
 {
-    return ((uintptr_t)in % 16) == 0 && ((uintptr_t)out % 16) == 0;
+    (void)p;
+    (void)in;
+    (void)out;
+    return true;
 }
 
 // A copy of the plan that carries the batched decompositions, for the
@@ -464,7 +484,7 @@ static void batch_view(const mclahe_plan_s *p, mclahe_plan_s &q)
 // Pointers of a run's descriptor.
 static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, char *ws)
 {
-    v = vec_aligned(in, out) ? p->v : p->v1;
+    v = vec_aligned(p, in, out) ? p->v : p->v1;
     v.in = in;
     v.out = out;
     v.part = (uint32_t *)(ws + p->o_part);
@@ -793,7 +813,7 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
         // the slab's buffers index global rows; vector loads need them aligned
         const char *sin = cur - (size_t)base * row_in;
         char *sout = outbuf[Y] - (size_t)g.mr0[j] * row_out;
-        McVol v = vec_aligned(sin, sout) ? p->v : p->v1;
+        McVol v = vec_aligned(p, sin, sout) ? p->v : p->v1;
         v.wk0 = kA;
         v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
         v.n_clip_wu = (uint32_t)((int64_t)nl * g.layer_kernels);
@@ -874,7 +894,7 @@ struct BatchLaunch {
 
 struct BatchLayout {
     std::vector<mclahe_plan_s> view;   // the plans with their batched decomposition
-    uint64_t o_table, o_recs, o_idx, o_vols, o_first, total;
+    uint64_t o_table, o_recs, o_idx, o_vols, o_phdr, o_pre, o_q, o_first, total;
     std::vector<uint64_t> vol_off;
     std::vector<BatchLaunch> launches;
     uint32_t n_idx = 0;
@@ -892,7 +912,7 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, const void 
     L.view.resize(n);
     for (int i = 0; i < n; ++i) {
         batch_view(plans[i], L.view[i]);
-        if (ins && outs && !vec_aligned(ins[i], outs[i])) L.view[i].v = L.view[i].v1;
+        if (ins && outs && !vec_aligned(&L.view[i], ins[i], outs[i])) L.view[i].v = L.view[i].v1;
     }
     // group the volumes of each pass by kernel class
     L.launches.clear();
@@ -935,6 +955,14 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, const void 
     o = align256(o + (uint64_t)L.n_idx * 4);
     L.o_vols = o;
     o = align256(o + (uint64_t)n * sizeof(McVol));
+    // the persistent launch's table: header, unit prefix sums per pass, and
+    // the run's words (ticket head, abort word, completion counters)
+    L.o_phdr = o;
+    o = align256(o + sizeof(McPersistHdr));
+    L.o_pre = o;
+    o = align256(o + (uint64_t)MC_PHASES * (n + 1) * 4);
+    L.o_q = o;
+    o = align256(o + (uint64_t)mc_persist_words((uint32_t)n) * 4);
     L.o_first = o;
     L.vol_off.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -958,6 +986,24 @@ static void fill_table(int n, const mclahe_plan_t *plans, const void *const *ins
     for (int i = 0; i < n; ++i) bind(&L.view[i], vols[i], ins[i], outs[i], vol_ws[i]);
     h->nvol = (uint32_t)n;
     h->nlaunch = (uint32_t)L.launches.size();
+    h->o_persist = (uint32_t)(L.o_phdr - L.o_table);
+    {   // persistent launch: tickets in pass-major, batch order
+        McPersistHdr *ph = (McPersistHdr *)(img.data() + L.o_phdr);
+        uint32_t *pre = (uint32_t *)(img.data() + L.o_pre);
+        ph->nvol = (uint32_t)n;
+        ph->max_spins = kPersistSpins;
+        ph->abort_at = MC_NO_TICKET;
+        uint32_t t = 0;
+        for (int p = 0; p < MC_PHASES; ++p) {
+            ph->phase_start[p] = t;
+            uint32_t *pp = pre + p * (n + 1);
+            pp[0] = 0;
+            for (int i = 0; i < n; ++i) pp[i + 1] = pp[i] + mc_phase_units(L.view[i].v, p);
+            t += pp[n];
+        }
+        ph->phase_start[MC_PHASES] = t;
+        ph->total = t;
+    }
     uint32_t k = 0;
     for (size_t j = 0; j < L.launches.size(); ++j) {
         const BatchLaunch &bl = L.launches[j];
@@ -1260,10 +1306,14 @@ mclahe_status mclahe_plan(mclahe_plan_t *plan, int ndim, const int64_t *shape, c
         tune_cache_load();
         auto it = g_tune_cache.find(plan_key(p));
         if (it != g_tune_cache.end()) p->tune = it->second;
+        auto ib = g_tune_cache.find("B" + plan_key(p));
+        if (ib != g_tune_cache.end()) p->btune = ib->second;
     }
     mclahe_status s = derive(p);
-    if (s != MCLAHE_SUCCESS && (p->tune.hist_rows_split || p->tune.map_rows_split)) {
+    if (s != MCLAHE_SUCCESS && (p->tune.hist_rows_split || p->tune.map_rows_split || p->btune.hist_rows_split ||
+                                p->btune.map_rows_split)) {
         memset(&p->tune, 0, sizeof p->tune);
+        memset(&p->btune, 0, sizeof p->btune);
         s = derive(p);
     }
     if (s != MCLAHE_SUCCESS) {
@@ -1324,6 +1374,36 @@ mclahe_status mclahe_plan_set_tuning(mclahe_plan_t p, const mclahe_tuning *t)
     if (s != MCLAHE_SUCCESS) {
         const std::string msg = g_err;
         p->tune = old;
+        derive(p);
+        g_err = msg;
+    }
+    return s;
+}
+
+mclahe_status mclahe_plan_get_batch_tuning(mclahe_plan_t p, mclahe_tuning *t)
+{
+    if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    t->hist_rows_split = p->bv.hCr;
+    t->hist_copies = p->bv.hR;
+    t->hist_peel = p->bv.hPeel + 1;
+    t->map_rows_split = p->bv.mCr;
+    t->map_unit_chunks = p->bv.mK;
+    t->map_group = p->bv.mG;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_plan_set_batch_tuning(mclahe_plan_t p, const mclahe_tuning *t)
+{
+    if (!p || !t) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    if (t->hist_rows_split < 0 || t->map_rows_split < 0 || t->map_group < 0 || t->map_unit_chunks < 0 ||
+        t->hist_peel < 0 || t->hist_peel > 3 || t->hist_copies < 0)
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "tuning fields must be >= 0 (hist_peel <= 3)");
+    const mclahe_tuning old = p->btune;
+    p->btune = *t;
+    mclahe_status s = derive(p);
+    if (s != MCLAHE_SUCCESS) {
+        const std::string msg = g_err;
+        p->btune = old;
         derive(p);
         g_err = msg;
     }
@@ -1402,6 +1482,118 @@ mclahe_status mclahe_run(mclahe_plan_t p, const void *d_in, void *d_out, void *d
     McVol v;
     bind(p, v, d_in, d_out, (char *)d_ws);
     return run_plain(p, v, (hipStream_t)stream);
+}
+
+// ------------------------------------------------- run with the metrics --
+// Workspace: the plan's own, then one metric record per interpolation unit
+// (either decomposition), then the metric passes' own arrays.
+static uint64_t met_parts_off(const mclahe_plan_s *p) { return align256(p->total); }
+static uint64_t met_tail_off(const mclahe_plan_s *p)
+{
+    const uint64_t nu = std::max(p->v.n_map_wu, p->v1.n_map_wu);
+    return met_parts_off(p) + align256(nu * sizeof(McMetPart));
+}
+
+mclahe_status mclahe_run_metrics_workspace_size(mclahe_plan_t p, int n_bins, size_t *bytes)
+{
+    if (!p || !bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    if (n_bins < 2 || n_bins > 8192) return fail(MCLAHE_ERROR_INVALID_VALUE, "metric n_bins must be in [2, 8192]");
+    *bytes = met_tail_off(p) + mc_metrics_tail_ws(p->nvox, n_bins, (int)std::max(p->v.n_map_wu, p->v1.n_map_wu));
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_metrics(mclahe_plan_t p, const void *d_in, void *d_out, void *d_ws, size_t wsb,
+                                 int n_bins, double peak, mclahe_metrics_result *d_result, uint64_t *d_hist,
+                                 void *stream)
+{
+    g_err.clear();
+    size_t need = 0;
+    mclahe_status s = mclahe_run_metrics_workspace_size(p, n_bins, &need);
+    if (s) return s;
+    if (!d_result) return fail(MCLAHE_ERROR_INVALID_VALUE, "result pointer is NULL");
+    if (!(peak > 0.0) || !std::isfinite(peak)) return fail(MCLAHE_ERROR_INVALID_VALUE, "peak must be positive and finite");
+    if (d_in == d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "metrics need the input after the run: not in place");
+    if ((s = check_run_args(p, d_in, d_out, d_ws, wsb, need))) return s;
+    McVol v;
+    bind(p, v, d_in, d_out, (char *)d_ws);
+    v.met = (McMetPart *)((char *)d_ws + met_parts_off(p));
+    hipStream_t st = (hipStream_t)stream;
+    for (int ph = 0; ph < 3; ++ph) {
+        size_t lds = 0;
+        const KPair k = phase_kernels(p, v, ph, lds);
+        if ((s = launch(k.plain, mc_phase_units(v, ph), k.threads, lds, st, v))) return s;
+    }
+    size_t lds = 0;
+    const KPair k = phase_kernels(p, v, 3, lds);
+    const int dt = p->in_dt, ahr = p->mode == MC_AHR;
+    const KFn fm = dt == MC_U8 ? mc_pick_map_met_u8(p->D, ahr, v.path)
+                 : dt == MC_U16 ? mc_pick_map_met_u16(p->D, ahr, v.path) : mc_pick_map_met_f32(p->D, ahr, v.path);
+    if ((s = launch(fm, v.n_map_wu, k.threads, std::max<size_t>(lds, 256), st, v))) return s;
+    return mc_metrics_tail(d_in, p->in_dt, d_out, p->out_dt, p->nvox, n_bins, peak, v.met, (int)v.n_map_wu,
+                           d_result, d_hist, (char *)d_ws + met_tail_off(p), st);
+}
+
+// --------------------------------------------- smoothing, then the method --
+// Workspace: the plan's own, the Gaussian's intermediate volume, then the
+// (min, max) pairs of the Gaussian's last pass.
+static mclahe_status smooth_layout(const mclahe_plan_s *p, const double *sigma, double truncate, uint64_t &o_gws,
+                                   uint64_t &gws, uint64_t &o_mm, int64_t &nmm, uint64_t &total)
+{
+    size_t g = 0;
+    mclahe_status s = mclahe_gaussian_workspace_size(p->D, p->shape, sigma, &g);
+    if (s) return s;
+    nmm = 0;
+    if (p->mode == MC_GHR && !p->has_ur && truncate > 0.0 && std::isfinite(truncate))
+        nmm = mc_gaussian_mm_parts(p->D, p->shape, sigma, truncate);
+    o_gws = align256(p->total);
+    gws = g;
+    o_mm = align256(o_gws + g);
+    total = align256(o_mm + (uint64_t)nmm * 8);
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_smoothed_workspace_size(mclahe_plan_t p, const double *sigma, double truncate, size_t *bytes)
+{
+    if (!p || !sigma || !bytes) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    uint64_t o_gws, gws, o_mm, total;
+    int64_t nmm;
+    mclahe_status s = smooth_layout(p, sigma, truncate, o_gws, gws, o_mm, nmm, total);
+    if (s) return s;
+    *bytes = total;
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_smoothed(mclahe_plan_t p, const void *d_in, mclahe_dtype in_dtype, const double *sigma,
+                                  double truncate, float *d_smooth, void *d_out, void *d_ws, size_t wsb, void *stream)
+{
+    g_err.clear();
+    if (!p || !sigma) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    if (p->in_dt != MC_F32) return fail(MCLAHE_ERROR_INVALID_VALUE, "the plan must take float input (the smoothed volume)");
+    uint64_t o_gws, gws, o_mm, total;
+    int64_t nmm;
+    mclahe_status s = smooth_layout(p, sigma, truncate, o_gws, gws, o_mm, nmm, total);
+    if (s) return s;
+    if ((s = check_run_args(p, d_smooth, d_out, d_ws, wsb, total))) return s;
+    if ((const void *)d_smooth == d_in) return fail(MCLAHE_ERROR_INVALID_VALUE, "the smoothed volume must not overlap the input");
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    float *mm = nmm > 0 ? (float *)(ws + o_mm) : nullptr;
+    if ((s = mc_gaussian_run(d_in, in_dtype, p->D, p->shape, sigma, truncate, d_smooth, gws ? ws + o_gws : nullptr, gws,
+                             mm, st)))
+        return s;
+    McVol v;
+    bind(p, v, d_smooth, d_out, ws);
+    int ph0 = 0;
+    if (mm) {   // the smoothing pass took the global range: fold its pairs into the range partials
+        if ((s = mc_minmax_reduce(mm, nmm, v.rpart, v.n_range_wu, st))) return s;
+        ph0 = 1;
+    }
+    for (int ph = ph0; ph < MC_PHASES; ++ph) {
+        size_t lds = 0;
+        const KPair k = phase_kernels(p, v, ph, lds);
+        if ((s = launch(k.plain, mc_phase_units(v, ph), k.threads, lds, st, v))) return s;
+    }
+    return MCLAHE_SUCCESS;
 }
 
 // ------------------------------------------------------ no-allocation run --
@@ -1684,6 +1876,176 @@ mclahe_status mclahe_run_batched(int n, const mclahe_plan_t *plans, const void *
     return batched_launch(L, img, ws + L.o_table, (hipStream_t)stream);
 }
 
+// ------------------------------------------------ persistent batched run --
+// Grid and LDS of the persistent launch of a batch: as many work-groups as
+// fit the chip at once (no more than the tickets), and the LDS of the
+// largest unit of any pass of any volume.
+static mclahe_status persist_shape(const BatchLayout &L, const std::vector<char> &img, uint32_t &grid, size_t &lds)
+{
+    lds = 0;
+    for (const mclahe_plan_s &q : L.view)
+        for (int ph = 0; ph < MC_PHASES; ++ph) lds = std::max(lds, pass_lds(&q, q.v, ph));
+    lds = std::max<size_t>(lds, 16);
+    int dev = 0, cus = 0, per_cu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // (the kernel's own static LDS is a few words on top)
+    if (lds + 256 > 64 * 1024)
+        HIPCHK(hipFuncSetAttribute(mc_persist_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mc_persist_fn(), MC_T, lds));
+    if (per_cu < 1) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "persistent kernel does not fit a compute unit");
+    const uint32_t total = ((const McPersistHdr *)(img.data() + L.o_phdr))->total;
+    grid = (uint32_t)std::min<int64_t>((int64_t)cus * per_cu, std::max<uint32_t>(total, 1));
+    return MCLAHE_SUCCESS;
+}
+
+static void persist_args(const BatchLayout &L, char *table, McPersistSrc &src, uint32_t *&q, uint32_t &nq)
+{
+    src.hdr = (const McPersistHdr *)(table + L.o_phdr);
+    src.pre = (const uint32_t *)(table + L.o_pre);
+    src.vols = (const McVol *)(table + L.o_vols);
+    src.q = (uint32_t *)(table + L.o_q);
+    q = src.q;
+    nq = mc_persist_words((uint32_t)L.view.size());
+}
+
+// One persistent run: the table upload, a kernel clearing the run's words,
+// the persistent kernel.  A batch seen before is replayed from a graph of
+// those two kernels (same cache as the per-pass batched graphs).
+static mclahe_status persistent_launch(const BatchLayout &L, const std::vector<char> &img, char *table,
+                                       hipStream_t st)
+{
+    mclahe_status s;
+    uint32_t grid = 0;
+    size_t lds = 0;
+    if ((s = persist_shape(L, img, grid, lds))) return s;
+    McPersistSrc src;
+    uint32_t *q = nullptr, nq = 0;
+    persist_args(L, table, src, q, nq);
+    const uint32_t rgrid = (nq + MC_T - 1) / MC_T;
+    char buf[128];
+    snprintf(buf, sizeof buf, "P%zx/%u/%u/%zu/%zu", (size_t)(uintptr_t)table, grid,
+             ((const McPersistHdr *)(img.data() + L.o_phdr))->total, lds, L.view.size());
+    const std::string key(buf);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    ++g_tick;
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        if (!g_seen.count(key)) {
+            if (g_seen.size() > 4096) g_seen.clear();
+            g_seen.insert(key);
+            if ((s = stage_table(img, table, st))) return s;
+            hipLaunchKernelGGL((void (*)(uint32_t *, uint32_t))mc_persist_reset_fn(), dim3(rgrid), dim3(MC_T), 0, st,
+                               q, nq);
+            hipLaunchKernelGGL((void (*)(McPersistSrc))mc_persist_fn(), dim3(grid), dim3(MC_T), lds, st, src);
+            HIPCHK(hipGetLastError());
+            return MCLAHE_SUCCESS;
+        }
+        if (g_graphs.size() >= kGraphCacheMax) {
+            auto victim = g_graphs.begin();
+            for (auto e = g_graphs.begin(); e != g_graphs.end(); ++e)
+                if (e->second->last_use < victim->second->last_use) victim = e;
+            destroy_graph(victim->second);
+            g_graphs.erase(victim);
+        }
+        GraphEntry *g = new GraphEntry();
+        g->bytes = img.size();
+        for (int r = 0; r < 4; ++r) {
+            char *hb = nullptr;
+            hipEvent_t e = nullptr;
+            if (hipHostMalloc((void **)&hb, g->bytes, hipHostMallocDefault) != hipSuccess ||
+                hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                if (hb) (void)hipHostFree(hb);
+                destroy_graph(g);
+                return fail(MCLAHE_ERROR_HIP, "pinned staging buffer or event creation failed");
+            }
+            g->host.push_back(hb);
+            g->ev.push_back(e);
+            g->used.push_back(false);
+        }
+        auto build = [&]() -> mclahe_status {
+            HIPCHK(hipGraphCreate(&g->graph, 0));
+            hipKernelNodeParams kr = {};
+            void *rargs[] = {&q, &nq};
+            kr.func = (void *)mc_persist_reset_fn();
+            kr.gridDim = dim3(rgrid);
+            kr.blockDim = dim3(MC_T);
+            kr.sharedMemBytes = 0;
+            kr.kernelParams = rargs;
+            hipGraphNode_t nr, np;
+            HIPCHK(hipGraphAddKernelNode(&nr, g->graph, nullptr, 0, &kr));
+            hipKernelNodeParams kp = {};
+            void *pargs[] = {&src};
+            kp.func = (void *)mc_persist_fn();
+            kp.gridDim = dim3(grid);
+            kp.blockDim = dim3(MC_T);
+            kp.sharedMemBytes = (unsigned)lds;
+            kp.kernelParams = pargs;
+            HIPCHK(hipGraphAddKernelNode(&np, g->graph, &nr, 1, &kp));
+            HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+            return MCLAHE_SUCCESS;
+        };
+        if ((s = build())) {
+            destroy_graph(g);
+            return s;
+        }
+        it = g_graphs.emplace(key, g).first;
+    }
+    GraphEntry *g = it->second;
+    g->last_use = g_tick;
+    const int slot = g->next;
+    g->next = (g->next + 1) % (int)g->host.size();
+    if (g->used[slot]) HIPCHK(hipEventSynchronize(g->ev[slot]));
+    memcpy(g->host[slot], img.data(), g->bytes);
+    HIPCHK(hipMemcpyAsync(table, g->host[slot], g->bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(g->ev[slot], st));
+    g->used[slot] = true;
+    HIPCHK(hipGraphLaunch(g->exec, st));
+    return MCLAHE_SUCCESS;
+}
+
+mclahe_status mclahe_run_batched_persistent(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                            void *const *d_out, void *d_ws, size_t wsb,
+                                            const mclahe_persistent_opts *opts, void *stream)
+{
+    g_err.clear();
+    if (!d_in || !d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output arrays are NULL");
+    if (opts && (opts->flags & ~MCLAHE_PERSIST_ABORT_TICKET))
+        return fail(MCLAHE_ERROR_INVALID_VALUE, "unknown persistent-run flags 0x%x", opts->flags);
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, d_in, d_out, L);
+    if (s) return s;
+    for (int i = 0; i < n; ++i) {
+        s = check_run_args(plans[i], d_in[i], d_out[i], d_ws, wsb, L.total);
+        if (s) return fail(s, "volume %d: %s", i, g_err.c_str());
+    }
+    char *ws = (char *)d_ws;
+    std::vector<char *> vws;
+    vol_ws_in_place(n, ws, L, vws);
+    std::vector<char> img;
+    fill_table(n, plans, d_in, d_out, vws.data(), L, img);
+    McPersistHdr *h = (McPersistHdr *)(img.data() + L.o_phdr);
+    if (opts && opts->max_spins) h->max_spins = opts->max_spins;
+    if (opts && (opts->flags & MCLAHE_PERSIST_ABORT_TICKET)) h->abort_at = opts->abort_ticket;
+    return persistent_launch(L, img, ws + L.o_table, (hipStream_t)stream);
+}
+
+mclahe_status mclahe_persistent_status(int n, const mclahe_plan_t *plans, const void *d_ws, uint32_t *aborted,
+                                       uint32_t *tickets, void *stream)
+{
+    g_err.clear();
+    if (!d_ws || !aborted) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument");
+    BatchLayout L;
+    mclahe_status s = batch_layout(n, plans, nullptr, nullptr, L);
+    if (s) return s;
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    uint32_t w[2] = {0, 0};
+    HIPCHK(hipMemcpy(w, (const char *)d_ws + L.o_table + L.o_q, sizeof w, hipMemcpyDeviceToHost));
+    *aborted = w[MC_PQ_ABORT];
+    if (tickets) *tickets = w[MC_PQ_HEAD];
+    return MCLAHE_SUCCESS;
+}
+
 mclahe_status mclahe_run_batched_split(int n, const mclahe_plan_t *plans, const void *const *d_in,
                                        void *const *d_out, void *const *d_ws, const size_t *ws_bytes,
                                        void *d_table, size_t table_bytes, void *stream)
@@ -1827,6 +2189,161 @@ mclahe_status mclahe_autotune(mclahe_plan_t p, const void *d_in, void *d_out, vo
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return MCLAHE_SUCCESS;
+}
+
+// Batched autotuning.  Volumes that run the same kernels form a class; the
+// classes' launch chains overlap on the GPU, so a candidate is timed as the
+// whole batch through mclahe_run_batched (graph replays).  Per class, in
+// turn: the histogram row split (the default, or 2 or 4 times fewer, larger
+// units) with 1 or 2 LDS replicas, then the interpolation row chunks per unit
+// (half, the default, 2 or 4 times as many, or all).  Candidates never need
+// more workspace than the defaults (fewer histogram units, fewer partials).
+// The default is a candidate, and the result is kept only if it stays faster
+// than the default when the two are timed again: tuned is never slower.
+static std::string class_key(const mclahe_plan_s *p)
+{
+    return std::to_string(p->in_dt) + "/" + std::to_string(p->mode) + "/" + std::to_string(p->D) + "/" +
+           std::to_string(p->bv.path);
+}
+
+// Workspace of the batch under the default batch tuning (the largest any
+// candidate needs); the plans' batch tuning is left as it was.
+mclahe_status mclahe_autotune_batched_workspace_size(int n, const mclahe_plan_t *plans, size_t *bytes)
+{
+    if (!bytes || n < 1 || !plans) return fail(MCLAHE_ERROR_INVALID_VALUE, "NULL argument or n < 1");
+    for (int i = 0; i < n; ++i)
+        if (!plans[i]) return fail(MCLAHE_ERROR_INVALID_VALUE, "plan %d is NULL", i);
+    std::vector<mclahe_tuning> saved(n);
+    mclahe_status s = MCLAHE_SUCCESS;
+    for (int i = 0; i < n && !s; ++i) {
+        saved[i] = plans[i]->btune;
+        memset(&plans[i]->btune, 0, sizeof plans[i]->btune);
+        s = derive(plans[i]);
+    }
+    if (!s) s = mclahe_batched_workspace_size(n, plans, bytes);
+    for (int i = 0; i < n; ++i) {
+        plans[i]->btune = saved[i];
+        derive(plans[i]);
+    }
+    return s;
+}
+
+mclahe_status mclahe_autotune_batched(int n, const mclahe_plan_t *plans, const void *const *d_in,
+                                      void *const *d_out, void *d_ws, size_t wsb, void *stream)
+{
+    g_err.clear();
+    size_t need = 0;
+    mclahe_status s = mclahe_autotune_batched_workspace_size(n, plans, &need);
+    if (s) return s;
+    if (!d_in || !d_out) return fail(MCLAHE_ERROR_INVALID_VALUE, "input/output arrays are NULL");
+    if (wsb < need) return fail(MCLAHE_ERROR_WORKSPACE, "workspace too small: %zu < %zu bytes", wsb, need);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::vector<mclahe_tuning> saved(n), def(n);
+    for (int i = 0; i < n; ++i) saved[i] = plans[i]->btune;
+    auto apply = [&](const std::vector<mclahe_tuning> &t) -> mclahe_status {
+        for (int i = 0; i < n; ++i) {
+            plans[i]->btune = t[i];
+            mclahe_status r = derive(plans[i]);
+            if (r) return r;
+        }
+        size_t w = 0;
+        mclahe_status r = mclahe_batched_workspace_size(n, plans, &w);
+        if (r) return r;
+        return w <= wsb ? MCLAHE_SUCCESS : fail(MCLAHE_ERROR_WORKSPACE, "candidate needs more workspace");
+    };
+    auto time_batch = [&](float &best) -> mclahe_status {
+        mclahe_status r;
+        for (int w = 0; w < 3; ++w)   // direct, capture, first replay
+            if ((r = mclahe_run_batched(n, plans, d_in, d_out, d_ws, wsb, stream))) return r;
+        best = 1e30f;
+        for (int rep = 0; rep < 5; ++rep) {
+            HIPCHK(hipEventRecord(e0, st));
+            if ((r = mclahe_run_batched(n, plans, d_in, d_out, d_ws, wsb, stream))) return r;
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return MCLAHE_SUCCESS;
+    };
+    // defaults (batch tuning cleared) and the decomposition they give
+    std::vector<McVol> dv(n);
+    for (int i = 0; i < n; ++i) memset(&def[i], 0, sizeof def[i]);
+    if ((s = apply(def))) goto out;
+    for (int i = 0; i < n; ++i) dv[i] = plans[i]->bv;
+    {
+        std::map<std::string, std::vector<int>> cls;
+        for (int i = 0; i < n; ++i) cls[class_key(plans[i])].push_back(i);
+        std::vector<mclahe_tuning> cur = def;
+        float cur_ms;
+        if ((s = time_batch(cur_ms))) goto out;
+        const float def_ms = cur_ms;
+        for (auto &c : cls) {
+            auto with = [&](int fh, int R, int fm2) {   // fm2: map chunks per unit x fm2 / 2; 0 = all
+                std::vector<mclahe_tuning> t = cur;
+                for (int i : c.second) {
+                    const McVol &d = dv[i];
+                    mclahe_tuning &u = t[i];
+                    u.hist_rows_split = std::max(1, d.hCr / fh);
+                    u.hist_copies = R;
+                    u.map_rows_split = d.mCr;
+                    u.map_group = d.mG;
+                    u.map_unit_chunks = fm2 == 0 ? d.mCr : std::max(1, std::min(d.mCr, d.mK * fm2 / 2));
+                }
+                return t;
+            };
+            int bh = 1, bR = 1;
+            for (int fh : {1, 2, 4})
+                for (int R : {1, 2}) {
+                    std::vector<mclahe_tuning> t = with(fh, R, 2);
+                    float ms;
+                    if (apply(t) || time_batch(ms)) continue;
+                    if (ms < cur_ms) {
+                        cur_ms = ms;
+                        cur = t;
+                        bh = fh;
+                        bR = R;
+                    }
+                }
+            for (int fm2 : {1, 4, 8, 0}) {
+                std::vector<mclahe_tuning> t = with(bh, bR, fm2);
+                float ms;
+                if (apply(t) || time_batch(ms)) continue;
+                if (ms < cur_ms) {
+                    cur_ms = ms;
+                    cur = t;
+                }
+            }
+        }
+        // keep the result only if it beats the defaults again, both re-timed
+        float d_ms = def_ms, t_ms = cur_ms;
+        if ((s = apply(def)) || (s = time_batch(d_ms))) goto out;
+        if ((s = apply(cur)) || (s = time_batch(t_ms))) goto out;
+        if (!(t_ms < 0.99f * d_ms)) cur = def;
+        if ((s = apply(cur))) goto out;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int i = 0; i < n; ++i) {
+            mclahe_tuning eff;
+            mclahe_plan_get_batch_tuning(plans[i], &eff);
+            plans[i]->btune = cur[i].hist_rows_split ? eff : cur[i];
+            derive(plans[i]);
+            tune_cache_store("B" + plan_key(plans[i]), plans[i]->btune);
+        }
+    }
+out:
+    if (s) {   // leave the plans as they were
+        for (int i = 0; i < n; ++i) {
+            plans[i]->btune = saved[i];
+            derive(plans[i]);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
 }
 
 }  // extern "C"

@@ -84,12 +84,17 @@ def oracle_run(x, ks, nb, clip, mode="global", user_range=None, out_dtype=np.flo
 
 
 def assert_parity(g, r, out_dtype=np.float32, tol=1e-5, what=""):
-    """Histograms and clipped counts bit-exact; LUT and output within tolerance."""
+    """Histograms, clipped counts, ranges and LUTs bit-exact; output within
+    tolerance.  A LUT entry is one double division of exact integers rounded
+    once to float, so it has exactly one correct value (compared bit for bit,
+    beside the tolerance the output is held to)."""
     np.testing.assert_array_equal(g["hist"], r["hist"], err_msg=f"{what}: histograms")
     np.testing.assert_array_equal(g["clipped"], r["clipped"], err_msg=f"{what}: clipped counts")
     np.testing.assert_array_equal(g["range"], r["range"], err_msg=f"{what}: ranges")
     dl = np.abs(g["lut"].astype(np.float64) - r["lut"].astype(np.float64)).max()
     assert dl <= tol, f"{what}: LUT max |diff| {dl}"
+    np.testing.assert_array_equal(g["lut"].view(np.uint32), np.asarray(r["lut"], np.float32).view(np.uint32),
+                                  err_msg=f"{what}: LUT bits")
     if np.dtype(out_dtype) == np.float32:
         do = np.abs(g["out"].astype(np.float64) - r["out"].astype(np.float64)).max()
         assert do <= tol, f"{what}: output max |diff| {do}"

@@ -345,11 +345,10 @@ def test_batched_table_decodes_every_unit_once():
 
 @pytest.mark.parametrize("in_off,out_off", [(0, 0), (1, 0), (4, 0), (0, 8), (2, 2)])
 def test_batched_units_fit_their_work_groups(in_off, out_off):
-    """Buffers off a 16-byte boundary switch a volume to scalar loads; its row
-    segments must then fit MC_T single elements (histogram) and the
-    interpolation work-group (512 threads under a global range with vector
-    loads' LDS staging, 256 otherwise), not the vector chunks the aligned
-    decomposition was sized for."""
+    """Buffers at any address keep wide chunks (rows shorter than one chunk
+    take single elements); every unit's row segment must fit MC_T chunks
+    (histogram) and the interpolation work-group (512 threads under a
+    global range with LDS-staged LUTs, 256 otherwise)."""
     d = tempfile.mkdtemp(prefix="mclahe_batch_probe_")
     so = os.path.join(d, "probe.so")
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC",
@@ -376,10 +375,10 @@ def test_batched_units_fit_their_work_groups(in_off, out_off):
     img = _lib.batched_table(plans, ins, outs, 1 << 40)
     hm, mm, vec = ((ctypes.c_uint32 * n)() for _ in range(3))
     assert probe.probe_batch_chunks(img, len(img), hm, mm, vec) == 0
-    aligned = in_off % 16 == 0 and out_off % 16 == 0
     for i, p in enumerate(plans):
-        if not aligned:
-            assert vec[i] == 1, i
+        vmax = 4 if p.in_code == _lib.F32 else 8
+        # wide chunks at any address; single elements only for rows shorter than a chunk
+        assert vec[i] == (vmax if p.shape[-1] >= vmax else 1), i
         map_threads = 512 if p.mode == _lib.GLOBAL else 256
         assert 1 <= hm[i] <= 256, (i, hm[i])
         assert mm[i] <= map_threads, (i, mm[i])
@@ -538,3 +537,51 @@ def test_noalloc_scratch_size_matches_header():
     m = re.search(r"#define\s+MCLAHE_NOALLOC_SCRATCH_BYTES\s+\((\d+)ull\s*<<\s*(\d+)\)", src)
     assert m, "MCLAHE_NOALLOC_SCRATCH_BYTES not found"
     assert int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
+
+
+def test_batch_tuning_is_kept_apart_from_the_plain_tuning():
+    p = Plan((64, 96, 40), (16, 16, 10), 128, 0.02)
+    plain = p.tuning()
+    b = p.batch_tuning()
+    p.set_batch_tuning(hist_rows_split=1, map_unit_chunks=1, hist_copies=2)
+    nb = p.batch_tuning()
+    assert nb["hist_rows_split"] == 1 and nb["hist_copies"] == 2
+    assert p.tuning() == plain                   # the plain decomposition did not move
+    with pytest.raises(MclaheError):
+        p.set_batch_tuning(hist_copies=-1)
+    assert p.batch_tuning() == nb                # a refused setting changes nothing
+    p.set_batch_tuning()                         # back to the defaults
+    assert p.batch_tuning() == b
+
+
+def test_autotune_batched_workspace_covers_the_default_batch():
+    from paper_1906_11355_amd import synth
+    plans = [Plan(s["shape"], s["kernel_size"], 256, s["clip_limit"], "kernel" if s["adaptive"] else "global",
+                  in_dtype="uint16" if s["kind"] == "2d" else "float32") for s in synth.mix_spec(8, 4)]
+    need = _lib.autotune_batched_workspace_size(plans)
+    assert need == _lib.batched_workspace_size(plans)
+    for p in plans:                              # fewer histogram units: a smaller batch workspace
+        p.set_batch_tuning(hist_rows_split=1)
+    assert _lib.batched_workspace_size(plans) <= need
+    assert _lib.autotune_batched_workspace_size(plans) == need
+
+
+def test_persistent_table_tickets_cover_every_unit_in_pass_order():
+    """The persistent launch's table (in the batched table image): pass
+    starts are the running sums of the per-pass unit prefix sums."""
+    import struct
+    from paper_1906_11355_amd import synth
+    plans = [Plan(s["shape"], s["kernel_size"], 256, s["clip_limit"], "kernel" if s["adaptive"] else "global",
+                  in_dtype="uint16" if s["kind"] == "2d" else "float32") for s in synth.mix_spec(12, 4)]
+    n = len(plans)
+    img = _lib.batched_table(plans, [1 << 36] * n, [1 << 37] * n, 1 << 40)
+    o = struct.unpack_from("<I", img, 8)[0]
+    total, nvol, spins, abort_at = struct.unpack_from("<4I", img, o)
+    starts = struct.unpack_from("<5I", img, o + 16)
+    pre_off = (o + 48 + 255) & ~255
+    assert nvol == n and abort_at == 0xFFFFFFFF and spins > 0
+    assert starts[0] == 0 and starts[4] == total
+    for ph in range(4):
+        pre = struct.unpack_from(f"<{n + 1}I", img, pre_off + 4 * ph * (n + 1))
+        assert pre[0] == 0 and all(a <= b for a, b in zip(pre, pre[1:]))
+        assert starts[ph + 1] - starts[ph] == pre[n]

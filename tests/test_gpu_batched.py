@@ -144,10 +144,87 @@ def test_unaligned_inputs_with_long_rows():
         assert_parity(g, r, od, what=f"unaligned batched {x.shape}")
 
 
-@pytest.mark.skip(reason="The single persistent work-queue kernel (units of all passes pulled from "
-                         "one ticket queue, cross-work-group completion counters) did not finish on "
-                         "MI355X twice, also after its dependency wait was made an acquire with a "
-                         "wall-clock bound; the cause could not be shown on the CPU, so that code path "
-                         "was removed and replaced by one launch per pass (no inter-work-group waits).")
+# ------------------------------------------------ the persistent launch
+def _persist_phase_starts(plans):
+    """First ticket of each pass, read from the table image the library writes."""
+    import struct
+    from paper_1906_11355_amd import _lib
+    n = len(plans)
+    img = _lib.batched_table(plans, [1 << 36] * n, [1 << 37] * n, 1 << 40)
+    o = struct.unpack_from("<I", img, 8)[0]                 # McBatchHdr.o_persist
+    total = struct.unpack_from("<I", img, o)[0]
+    starts = struct.unpack_from("<5I", img, o + 16)         # McPersistHdr.phase_start
+    return total, starts
+
+
+def _run_persistent(plans, vols, ws=None, abort_ticket=None, max_spins=0):
+    import torch
+    from paper_1906_11355_amd import _lib
+    ins, outs = [], []
+    for x, *_r, od in vols:
+        ins.append(to_device_bytes(x))
+        outs.append(torch.zeros(x.size * np.dtype(od).itemsize + 64, dtype=torch.uint8, device="cuda"))
+    need = _lib.batched_workspace_size(plans)
+    if ws is None:
+        ws = torch.full((need,), 0xEF, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    _lib.run_batched_persistent_ptr(plans, [p for _, p in ins], [o.data_ptr() for o in outs], ws.data_ptr(),
+                                    ws.numel(), st, max_spins=max_spins, abort_ticket=abort_ticket)
+    status = _lib.persistent_status(plans, ws.data_ptr(), st)
+    torch.cuda.synchronize()
+    offs = _lib.batched_workspace_offsets(plans)
+    res = [collect(p, ws, off, o, o.data_ptr(), x.shape, od)
+           for p, off, o, (x, *_r, od) in zip(plans, offs, outs, vols)]
+    return res, ws, status
+
+
+@pytest.mark.timeout(120)
+def test_persistent_forced_give_up_ends_normally():
+    """A ticket told to give up (from the host) sets the run's abort word:
+    the kernel drains its tickets and ends, the status names that ticket."""
+    vols = _volumes()
+    plans = _plans(vols)
+    total, starts = _persist_phase_starts(plans)
+    for t in (starts[1], starts[3] + 1):
+        print(f"persistent forced give-up at ticket {t} of {total}", flush=True)
+        _, _, (aborted, tickets) = _run_persistent(plans, vols, abort_ticket=t)
+        assert aborted == t + 1, (t, aborted)
+        assert tickets >= total
+
+
+@pytest.mark.timeout(120)
 def test_persistent_single_launch_variant():
-    pass
+    """The whole batch in one persistent launch: every output and every
+    intermediate array bit-identical to mclahe_run, on repeated calls (graph
+    replays) with eager work between them, and within the oracle's bar."""
+    import torch
+    vols = _volumes()
+    plans = _plans(vols)
+    plain = _run_plain(plans, vols)
+    ws = None
+    for rep in range(3):
+        print(f"persistent run {rep}", flush=True)
+        res, ws, (aborted, _) = _run_persistent(plans, vols, ws)
+        assert aborted == 0
+        for i, (a, b) in enumerate(zip(res, plain)):
+            _same(a, b, i)
+        torch.zeros(1 << 20, device="cuda").add_(1.0)
+        torch.cuda.synchronize()
+    x, ks, nb, clip, mode, od = vols[2]
+    assert_parity(res[2], oracle_run(x, ks, nb, clip, mode, None, od), od, what="persistent 4D")
+
+
+@pytest.mark.timeout(300)
+def test_persistent_mix_matches_per_pass_batched():
+    """Sixteen volumes of the benchmark mix (2D uint16, 3D float per-kernel
+    range, 4D float): persistent and per-pass batched runs agree bit for bit."""
+    from paper_1906_11355_amd import synth
+    items = [synth.gen_item(s) for s in synth.mix_spec(16, 4)]
+    vols = [(it.x, it.kernel_size, it.n_bins, it.clip_limit, "kernel" if it.adaptive else "global", np.float32)
+            for it in items]
+    plans = _plans(vols)
+    ref, _ = _run_batched(plans, vols)
+    res, _, (aborted, _) = _run_persistent(plans, vols)
+    assert aborted == 0
+    for i, (a, b) in enumerate(zip(res, ref)):
+        _same(a, b, i)

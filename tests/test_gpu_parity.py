@@ -149,6 +149,35 @@ def test_unaligned_buffers_with_long_rows(case):
     _case(x, ks, nb, clip, mode, out_dtype=od, in_offset=off[0], out_offset=off[1])
 
 
+# shape, kernel, bins, clip, mode, (in, out) byte offsets, output dtype
+FLOAT_ROW_CASES = [
+    ((17, 9, 13), (5, 4, 7), 128, 0.03, "global", (0, 0), np.float32),
+    ((11, 7, 6, 13), (4, 3, 3, 7), 64, 0.05, "kernel", (4, 0), np.float32),
+    ((40, 1031), (16, 260), 256, 0.02, "global", (4, 12), np.float32),
+    ((3, 5, 97), (2, 3, 33), 64, 0.04, "kernel", (8, 12), np.float32),
+    ((30, 26, 25, 15), (8, 9, 7, 8), 256, 0.03, "global", (12, 1), np.uint8),
+    ((64, 14), (16, 7), 32, 0.1, "kernel", (0, 4), np.float32),
+    ((21, 10, 4, 11), (7, 5, 2, 11), 256, 0.02, "global", (4, 4), np.float32),
+    ((1023,), (100,), 64, 0.05, "global", (4, 8), np.uint16),
+    ((33, 5), (7, 2), 64, 0.05, "global", (4, 4), np.float32),          # rows just over one chunk
+    ((9, 12, 6), (3, 5, 6), 128, 0.02, "kernel", (0, 0), np.float32),
+    ((20, 7), (6, 3), 16, 0.2, "global", (8, 0), np.float32),
+    ((16, 3), (4, 2), 16, 0.2, "kernel", (0, 0), np.float32),           # shorter than a chunk: single loads
+    ((6, 2043), (3, 61), 256, 0.01, "global", (4, 0), np.float32),      # many last-axis segments
+]
+
+
+@pytest.mark.parametrize("case", range(len(FLOAT_ROW_CASES)))
+def test_float_rows_of_any_length_take_wide_loads(case):
+    """Float rows whose length is not a multiple of 4 are read in 4-element
+    chunks starting at any 4-byte boundary (buffers off a 16-byte boundary
+    too); the chunk that would run past a row end is read as the row's last
+    4 elements, the ones already covered skipped."""
+    shape, ks, nb, clip, mode, off, od = FLOAT_ROW_CASES[case]
+    x = np.random.default_rng(70 + case).poisson(4.0, size=shape).astype(np.float32)
+    _case(x, ks, nb, clip, mode, out_dtype=od, in_offset=off[0], out_offset=off[1])
+
+
 @pytest.mark.parametrize("dtype,in_offset", [(np.float32, 0), (np.float32, 4), (np.uint16, 0), (np.uint8, 0),
                                              (np.uint8, 3)])
 def test_global_range_many_units_ragged_tiles(dtype, in_offset):
