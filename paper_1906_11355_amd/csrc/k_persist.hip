@@ -10,13 +10,19 @@
 
 namespace {
 
-// Device side of the protocol's atomics.  A poll is an atomic
+// Device side of the protocol's atomics.  A peek is an agent-scope atomic
+// load (it may be served by the local L2, so it may see an older value).  A
+// poll is an atomic
 // read-modify-write at agent scope, performed where the updates of every
 // XCD meet whatever the local L2 holds: a compare-and-swap against a value
 // no run word ever takes, so it never stores and returns the current value
 // (an idempotent fetch-or or fetch-add would be turned into a plain load).
 // The abort word is set once, by compare-and-swap from zero.
 struct DevAtomics {
+    static __device__ __forceinline__ uint32_t peek(uint32_t *p)
+    {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     static __device__ __forceinline__ uint32_t poll(uint32_t *p)
     {
         uint32_t v = 0xffffffffu;
@@ -111,11 +117,12 @@ __global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s)
     const McPersistHdr &h = *s.hdr;
     const uint32_t total = h.total;
     uint32_t *prev = nullptr;   // thread 0: counter of the ticket it ran last
+    uint32_t prev_ph = MC_PHASES;   // pass of the previous ticket (uniform)
     for (;;) {
         // every thread's writes of the previous unit, visible device-wide
-        // before its counter moves (a skipped unit counts too: its waiters
-        // end anyway)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // before its counter moves.  Interpolation output is read by no
+        // later unit: no release after an interpolation unit.
+        if (prev_ph < MC_PHASES - 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (threadIdx.x == 0) {
             if (prev) __hip_atomic_fetch_add(prev, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -126,7 +133,12 @@ __global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s)
             if (t < total) {
                 k = mc_ticket(h, s.pre, t);
                 go = mc_persist_wait<DevAtomics>(h, s.pre, s.q, k, t) ? 1u : 0u;
-                prev = mc_persist_done(h, s.q, k);
+                // only a unit that ran counts: after an abort, the units of
+                // a skipped unit's volume wait and see the abort word instead
+                // of running on what the skipped one did not write
+                prev = go ? mc_persist_done(h, s.q, k) : nullptr;
+            } else {
+                prev = nullptr;
             }
             info[0] = t;
             info[1] = k.phase;
@@ -139,9 +151,11 @@ __global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s)
         const uint32_t vi = __builtin_amdgcn_readfirstlane(info[2]);
         const uint32_t uw = __builtin_amdgcn_readfirstlane(info[3]);
         if (t >= total) break;
+        prev_ph = ph;
         if (uw >> 31) {
-            // the producers' writes (released before their counters moved)
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // the producers' writes (released before their counters moved);
+            // the range pass reads only the input
+            if (ph > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const McVol &v = s.vols[vi];
             const uint32_t u = uw & 0x7fffffffu;
             if (v.in_dt == MC_U8) persist_unit<uint8_t>(v, ph, u, smem);

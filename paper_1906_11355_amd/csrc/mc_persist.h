@@ -16,11 +16,12 @@
 // ticket never waits on anything unfinished: the queue cannot deadlock.
 //
 // Every wait is bounded anyway.  A wait polls the volume's completion
-// counter of the previous pass and, before each poll, one abort word of the
-// whole run; after max_spins polls it sets the abort word and gives up.
-// Once the word is set, every later wait ends at once and every later unit
-// is skipped, so a run that cannot complete still drains its tickets and the
-// kernel ends normally; the word tells the host which ticket gave up.
+// counter of the previous pass and one abort word of the whole run; after
+// max_spins polls it sets the abort word and gives up.  Only units that ran
+// count, so once the word is set a unit whose producers were skipped never
+// runs: its wait ends on the word.  A run that cannot complete still drains
+// its tickets and the kernel ends normally; the word tells the host which
+// ticket gave up.
 #pragma once
 #include "mc_desc.h"
 
@@ -81,20 +82,24 @@ MC_HD uint32_t mc_persist_units(const McPersistHdr &h, const uint32_t *pre, uint
 
 // Wait until ticket t may run.  Returns true to run its unit, false to skip
 // it (the run was aborted, by this wait or an earlier one).  A: the atomic
-// operations (poll reads a word coherently, set_abort stores the first
-// abort only, sleep pauses between polls).
+// operations -- peek reads a word cheaply but possibly late (an older value:
+// counters only grow, so a peeked count at or above the need is final),
+// poll reads it coherently (dearer), set_abort stores the first abort only,
+// sleep pauses between polls.  Most tickets find their pass done already
+// and pass on two peeks; only a real wait polls.
 template <class A>
 MC_HD bool mc_persist_wait(const McPersistHdr &h, const uint32_t *pre, uint32_t *q, const McTicket &k,
                            uint32_t t)
 {
-    if (A::poll(&q[MC_PQ_ABORT])) return false;
     if (t == h.abort_at) {
         A::set_abort(&q[MC_PQ_ABORT], t + 1);
         return false;
     }
+    if (A::peek(&q[MC_PQ_ABORT])) return false;
     if (k.phase == 0) return true;
     const uint32_t need = mc_persist_units(h, pre, k.phase - 1, k.vol);
     uint32_t *cnt = &q[MC_PQ_DONE + (k.phase - 1) * h.nvol + k.vol];
+    if (A::peek(cnt) >= need) return true;
     for (uint32_t spins = 0;; ++spins) {
         if (A::poll(cnt) >= need) return true;
         if (A::poll(&q[MC_PQ_ABORT])) return false;
@@ -106,7 +111,7 @@ MC_HD bool mc_persist_wait(const McPersistHdr &h, const uint32_t *pre, uint32_t 
     }
 }
 
-// Counter a finished (or skipped) ticket increments.
+// Counter a ticket whose unit ran increments.
 MC_HD uint32_t *mc_persist_done(const McPersistHdr &h, uint32_t *q, const McTicket &k)
 {
     return &q[MC_PQ_DONE + k.phase * h.nvol + k.vol];
