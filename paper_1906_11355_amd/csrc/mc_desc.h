@@ -19,6 +19,8 @@
                            // bigger groups keep more waves in flight); the
                            // adaptive-range map, heavier in registers, uses MC_T
 #define MC_OMAX 256        // outer-row table entries per work unit
+#define MC_STAGE 8         // loads a thread keeps in flight while staging
+                           // per-kernel arrays (LUTs, partials) of a unit
 #define MC_LDS_BUDGET (64 * 1024)   // LDS a work unit may use (bytes)
 #define MC_NUM_CU 256      // MI355X compute units (tiling target)
 

@@ -462,10 +462,22 @@ __device__ __forceinline__ void ghr_range(const McVol &d, float *red, float &lo,
         lo = d.user_lo;
         hi = d.user_hi;
     } else {
+        // up to MC_STAGE partials per thread in flight at a time (a min and a
+        // max: exact in any order)
         float mn = INFINITY, mx = -INFINITY;
-        for (uint32_t i = threadIdx.x; i < d.n_range_wu; i += MC_T) {
-            mn = fminf(mn, d.rpart[2 * i]);
-            mx = fmaxf(mx, d.rpart[2 * i + 1]);
+        for (uint32_t i0 = threadIdx.x; i0 < d.n_range_wu; i0 += MC_STAGE * MC_T) {
+            float2 pv[MC_STAGE];
+#pragma unroll
+            for (int q = 0; q < MC_STAGE; ++q) {
+                const uint32_t i = i0 + (uint32_t)q * MC_T;
+                pv[q] = i < d.n_range_wu ? make_float2(d.rpart[2 * i], d.rpart[2 * i + 1])
+                                         : make_float2(INFINITY, -INFINITY);
+            }
+#pragma unroll
+            for (int q = 0; q < MC_STAGE; ++q) {
+                mn = fminf(mn, pv[q].x);
+                mx = fmaxf(mx, pv[q].y);
+            }
         }
         int *ri = (int *)red;
         if (threadIdx.x == 0) {
@@ -645,13 +657,28 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                 int sg0, nsg, sl;
                 if (d.hP == 1) { sg0 = seg; nsg = 1; sl = s; }
                 else { sg0 = k * d.hP; nsg = d.hP; sl = 0; }
+                // MC_STAGE partials in flight at a time, reduced in the
+                // order of the partials
                 float mn = INFINITY, mx = -INFINITY;
-                for (int g = 0; g < nsg; ++g)
-                    for (int c = 0; c < d.hCr; ++c) {
-                        const int64_t u = (cb + sg0 + g) * d.hCr + c;
-                        mn = fminf(mn, d.rpart[(u * d.hG + sl) * 2]);
-                        mx = fmaxf(mx, d.rpart[(u * d.hG + sl) * 2 + 1]);
+                const int np = nsg * d.hCr;
+                for (int p0 = 0; p0 < np; p0 += MC_STAGE) {
+                    float2 pv[MC_STAGE];
+#pragma unroll
+                    for (int q = 0; q < MC_STAGE; ++q) {
+                        const int pi = p0 + q;
+                        pv[q] = make_float2(INFINITY, -INFINITY);
+                        if (pi < np) {
+                            const int g = pi / d.hCr, c = pi - g * d.hCr;
+                            const int64_t u = (cb + sg0 + g) * d.hCr + c;
+                            pv[q] = make_float2(d.rpart[(u * d.hG + sl) * 2], d.rpart[(u * d.hG + sl) * 2 + 1]);
+                        }
                     }
+#pragma unroll
+                    for (int q = 0; q < MC_STAGE; ++q) {
+                        mn = fminf(mn, pv[q].x);
+                        mx = fmaxf(mx, pv[q].y);
+                    }
+                }
                 L.slot_lo[s] = mn;
                 L.slot_sc[s] = range_scale(nb, mn, mx);
                 if (chunk == 0 && (d.hP == 1 || seg % d.hP == 0)) {
@@ -914,13 +941,25 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
     const unsigned long long C = (unsigned long long)d.clipC;
     uint32_t *hk = d.hist + (int64_t)k * nb;
     unsigned long long smin = 0, exc = 0;
+    const int np = nsg * d.hCr;   // partials of this kernel
     for (int j = j0; j < j1; ++j) {
+        // MC_STAGE partials in flight at a time (integer sums: exact in any order)
         uint32_t h = 0;
-        for (int g = 0; g < nsg; ++g)
-            for (int c = 0; c < d.hCr; ++c) {
-                const int64_t u = (col * d.hS + sg0 + g) * d.hCr + c;
-                h += d.part[(u * d.hG + sl) * nb + j];
+        for (int p0 = 0; p0 < np; p0 += MC_STAGE) {
+            uint32_t pv[MC_STAGE];
+#pragma unroll
+            for (int q = 0; q < MC_STAGE; ++q) {
+                const int pi = p0 + q;
+                pv[q] = 0u;
+                if (pi < np) {
+                    const int g = pi / d.hCr, c = pi - g * d.hCr;
+                    const int64_t u = (col * d.hS + sg0 + g) * d.hCr + c;
+                    pv[q] = d.part[(u * d.hG + sl) * nb + j];
+                }
             }
+#pragma unroll
+            for (int q = 0; q < MC_STAGE; ++q) h += pv[q];
+        }
         hk[j] = h;
         smin += h < C ? h : C;
         exc += h > C ? h - C : 0ull;
@@ -1072,17 +1111,35 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     // different bins spread over the banks.  AHR: [lk*NO + corner'][bin].
     const int nlk = ncl + 1;
     const int SB = AHR ? 0 : mc_lut_stride(nlk, NO);
-    for (int t = 0; t < nlk * NO; ++t) {          // one kernel's LUT per step
-        const int co = t % NO, lk = t / NO;       // NO is a power of two
-        int64_t kid = kbase + cA + lk;
+    {
+        // every thread issues up to MC_STAGE loads before its first LDS
+        // store: one kernel's LUT per step would wait for memory once per
+        // staged kernel (2^(D-1) (mG + 1) of them), a fixed latency that
+        // dominated units of a few hundred thousand voxels
+        constexpr int ST = MC_STAGE;
+        const int tot = nlk * NO * nb;
+        for (int i0 = threadIdx.x; i0 < tot; i0 += ST * NT) {
+            float val[ST];
+            int dst[ST];
 #pragma unroll
-        for (int j = 0; j < D - 1; ++j)
-            if ((co >> (D - 2 - j)) & 1) kid += kst[j];
-        const float *src = d.lut + kid * nb;
-        if constexpr (AHR) {
-            for (int b = threadIdx.x; b < nb; b += NT) lut[t * nb + b] = src[b];
-        } else {
-            for (int b = threadIdx.x; b < nb; b += NT) lut[__umul24(b, SB) + lk * NO + co] = src[b];
+            for (int q = 0; q < ST; ++q) {
+                const int i = i0 + q * NT;
+                dst[q] = -1;
+                val[q] = 0.f;
+                if (i < tot) {
+                    const int t = i / nb, b = i - t * nb;
+                    const int co = t % NO, lk = t / NO;   // NO is a power of two
+                    int64_t kid = kbase + cA + lk;
+#pragma unroll
+                    for (int j = 0; j < D - 1; ++j)
+                        if ((co >> (D - 2 - j)) & 1) kid += kst[j];
+                    val[q] = d.lut[kid * nb + b];
+                    dst[q] = AHR ? i : __umul24(b, SB) + lk * NO + co;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < ST; ++q)
+                if (dst[q] >= 0) lut[dst[q]] = val[q];
         }
     }
     // per-corner ranges (AHR: one last-axis cell per unit)
