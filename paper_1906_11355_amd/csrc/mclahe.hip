@@ -111,7 +111,7 @@ static int64_t clip_count(double clip, int64_t K)
 static const int64_t kUnitVoxPlain = 16384, kUnitVoxBatch = 65536;
 // Voxels per interpolation unit a batched volume aims at under a global range
 // (a unit then stages its LUTs for about as many rows as at the 4D headline)
-static const int64_t kMapUnitVoxBatch = 262144;
+static const int64_t kMapUnitVoxBatch = 65536;
 // Polls of one wait of the persistent launch before the run gives up (each
 // poll an atomic and a short sleep: on the order of a second in all)
 static const uint32_t kPersistSpins = 1u << 20;
@@ -942,6 +942,20 @@ static mclahe_status batch_layout(int n, const mclahe_plan_t *plans, const void 
             bl->lds = std::max(bl->lds, lds);
             bl->vols.push_back((uint32_t)i);
             bl->pre.push_back(bl->pre.back() + units);
+        }
+        // Work-groups are dispatched in index order as the chip frees room:
+        // put the volumes with the largest units first, so that the launch
+        // ends on small units instead of waiting for a few large ones that
+        // started last (longest-first list scheduling).
+        for (size_t j = first; j < L.launches.size(); ++j) {
+            BatchLaunch &bl = L.launches[j];
+            auto per_unit = [&](uint32_t i) {
+                return (double)L.view[i].nvox / (double)mc_phase_units(L.view[i].v, ph);
+            };
+            std::stable_sort(bl.vols.begin(), bl.vols.end(),
+                             [&](uint32_t a, uint32_t b) { return per_unit(a) > per_unit(b); });
+            bl.pre.assign(1, 0u);
+            for (uint32_t i : bl.vols) bl.pre.push_back(bl.pre.back() + mc_phase_units(L.view[i].v, ph));
         }
     }
     L.n_idx = 0;
