@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mc_desc.h"
 
 namespace mc {
@@ -726,6 +728,19 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         mx[e] = -INFINITY;
     }
     const int cp = R > 1 ? (lane_id() & (R - 1)) : 0;
+    // Per element, the byte offset of its first slot's replica in the LDS
+    // histograms and its multiplicity; an element outside the segment adds
+    // weight 0 to slot 0 instead of branching.  A bin then costs one shift
+    // and add for its address and a 24-bit multiply for its weight.
+    uint32_t hoff[V], w1[V];
+    bool anyx = false;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        hoff[e] = m.s1[e] >= 0 ? (uint32_t)(m.s1[e] * SS + cp) * 4u : (uint32_t)cp * 4u;
+        w1[e] = m.s1[e] >= 0 ? m.w1[e] : 0u;
+        anyx = anyx || m.extra[e] != 0u;
+    }
+    const uint32_t bsh = 2u + (uint32_t)__builtin_ctz((unsigned)R);   // bin -> byte offset
     const Tin *in = (const Tin *)d.in;
     if (tact) {
         const int64_t rstart = r0 + trow;
@@ -758,17 +773,29 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
             for (int u = 0; u < U; ++u)
                 if (okk[u]) load_chunk<Tin, V>(in + offs[u], fl[u]);
         };
-        auto process = [&](int64_t rw, const uint32_t (&wr)[U], const bool (&okk)[U], const float (&fl)[U][V]) {
+        // XT: whether this wave has elements with further memberships (a
+        // wave-uniform value, so the loop without them is a separate copy
+        // that tests nothing per element)
+        auto process = [&](auto XT, int64_t rw, const uint32_t (&wr)[U], const bool (&okk)[U],
+                           const float (&fl)[U][V]) {
+            constexpr bool XW = decltype(XT)::value;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
             if (!okk[u]) break;
             const float (&f)[V] = fl[u];
             const uint32_t wrow = wr[u];
+            if constexpr (!RANGE_ONLY && PEEL == 0) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const uint32_t b = (uint32_t)bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
+                    atomicAdd((uint32_t *)((char *)L.h + ((b << bsh) + hoff[e])), __umul24(wrow, w1[e]));
+                }
+            }
             // LDS word of (slot, bin) per element (replica 0; -1: no update)
-            // and its weight
+            // and its weight (wavefront aggregation only)
             int key[V];
             uint32_t wk[V];
-            if constexpr (!RANGE_ONLY) {
+            if constexpr (!RANGE_ONLY && PEEL > 0) {
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     key[e] = -1;
@@ -778,6 +805,8 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                     }
                 }
             }
+            // the further memberships of elements near a fold
+            if constexpr (RANGE_ONLY || PEEL > 0 || XW) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 if constexpr (RANGE_ONLY) {
@@ -793,7 +822,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                         }
                     }
                 } else {
-                    hist_add<PEEL>(L.h, key[e], wk[e], cp);
+                    if constexpr (PEEL > 0) hist_add<PEEL>(L.h, key[e], wk[e], cp);
                     if (m.extra[e]) {
                         uint32_t ex = m.extra[e];
                         while (ex) {
@@ -808,24 +837,33 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                 }
             }
             }
+            }
         };
-        uint32_t wA[U], wB[U];
-        bool okA[U], okB[U];
-        float fA[U][V], fB[U][V];
-        const int64_t step = (int64_t)U * rpi;
-        int64_t row = rstart;
-        prep_load(row, wA, okA, fA);
-        for (;;) {
-            const int64_t nb = row + step;
-            if (nb < r1) prep_load(nb, wB, okB, fB);
-            process(row, wA, okA, fA);
-            row = nb;
-            if (row >= r1) break;
-            const int64_t na = row + step;
-            if (na < r1) prep_load(na, wA, okA, fA);
-            process(row, wB, okB, fB);
-            row = na;
-            if (row >= r1) break;
+        auto rows = [&](auto XT) {
+            uint32_t wA[U], wB[U];
+            bool okA[U], okB[U];
+            float fA[U][V], fB[U][V];
+            const int64_t step = (int64_t)U * rpi;
+            int64_t row = rstart;
+            prep_load(row, wA, okA, fA);
+            for (;;) {
+                const int64_t nb = row + step;
+                if (nb < r1) prep_load(nb, wB, okB, fB);
+                process(XT, row, wA, okA, fA);
+                row = nb;
+                if (row >= r1) break;
+                const int64_t na = row + step;
+                if (na < r1) prep_load(na, wA, okA, fA);
+                process(XT, row, wB, okB, fB);
+                row = na;
+                if (row >= r1) break;
+            }
+        };
+        if constexpr (RANGE_ONLY || PEEL > 0) {
+            rows(std::true_type{});
+        } else {
+            if (__any(anyx ? 1 : 0)) rows(std::true_type{});
+            else rows(std::false_type{});
         }
     }
     if constexpr (RANGE_ONLY) {
