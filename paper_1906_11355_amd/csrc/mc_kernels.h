@@ -103,6 +103,15 @@ __device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)
     }
 }
 
+// A read-only descriptor in device memory, seen through the constant
+// address space: loads from it are known not to be clobbered by the kernel's
+// stores, so its fields stay in registers (scalar loads) once read.
+__device__ __forceinline__ const McVol &mc_const_desc(const McVol *p)
+{
+    typedef const __attribute__((address_space(4))) McVol CMcVol;
+    return *(const McVol *)(CMcVol *)p;
+}
+
 __device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
 {
     if (dt == MC_U8) return (float)((const uint8_t *)in)[i];
@@ -1083,6 +1092,31 @@ __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int
 // m / (2b) as m times the single-precision reciprocal of 2b (exact for
 // power-of-two b, otherwise within one ulp; the same expression is used by
 // every kernel, so plain and batched results stay bit-identical).
+// Uniform copies of descriptor fields: scalar registers that the compiler
+// keeps for a whole loop.  The batched kernels read their descriptor from
+// device memory, and a field read inside a loop that stores to memory would
+// otherwise be reloaded (with a vector load) on every iteration.
+__device__ __forceinline__ int32_t mc_uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename T>
+__device__ __forceinline__ T *mc_uniform_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ McAxis mc_uniform_axis(const McAxis &a)
+{
+    McAxis r;
+    r.s = mc_uniform(a.s);
+    r.b = mc_uniform(a.b);
+    r.p0 = mc_uniform(a.p0);
+    r.p1 = mc_uniform(a.p1);
+    r.n = mc_uniform(a.n);
+    r.cw = mc_uniform(a.cw);
+    return r;
+}
+
 __device__ __forceinline__ float cell_weight(const McAxis &a, int c, int x)
 {
     return (float)mc_cell_m(a, c, x) * (1.0f / (float)(2 * a.b));
@@ -1246,7 +1280,12 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int nbm1 = nb - 1;
     const int64_t so = rpi / rs.in_len;
     const int sr = (int)(rpi - so * rs.in_len);
-    const bool vecst = (d.out_dt == MC_F32) && (V % 4 == 0) && allv;
+    // descriptor fields of the row loop, held in scalar registers
+    const McAxis aw = mc_uniform_axis(d.ax[D >= 2 ? D - 2 : 0]);
+    void *const outp = mc_uniform_ptr(d.out);
+    const int out_dt = mc_uniform(d.out_dt);
+    const bool ntst = mc_uniform(d.ntst) != 0;
+    const bool vecst = (out_dt == MC_F32) && (V % 4 == 0) && allv;
     // the unit's row chunks, one after another on the same staged LUTs; the
     // outer-row table is rebuilt for each chunk
     // (per-kernel range: one chunk per unit, which keeps its 2^D ranges in
@@ -1302,7 +1341,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                 const OT &te = otab[ok[u] ? (int)(o - o0) : 0];
                 const int xin = rs.in_lo + r;
                 offs[u] = te.off + (int64_t)xin * rs.in_stride + xoff;
-                win[u] = D >= 2 ? cell_weight(d.ax[D >= 2 ? D - 2 : 0], cidx[D >= 2 ? D - 2 : 0], xin) : 0.f;
+                win[u] = D >= 2 ? cell_weight(aw, cidx[D >= 2 ? D - 2 : 0], xin) : 0.f;
 #pragma unroll
                 for (int q = 0; q < NOH; ++q) cfu[u][q] = D >= 3 ? te.coef[q] : 1.0f;
                 r += sr;
@@ -1378,8 +1417,8 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                     // otherwise write-back stores let L2 merge the parts of a
                     // line that neighbouring units write
                     if constexpr (V % 4 == 0) {
-                        f4 *op = (f4 *)((float *)d.out + off);
-                        if (d.ntst) {
+                        f4 *op = (f4 *)((float *)outp + off);
+                        if (ntst) {
 #pragma unroll
                             for (int q = 0; q < V / 4; ++q) {
                                 f4 t = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
@@ -1393,12 +1432,12 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
                 } else {
 #pragma unroll
                     for (int e = 0; e < V; ++e)
-                        if (val[e]) store_elem(d.out, d.out_dt, off + e, y[e]);
+                        if (val[e]) store_elem(outp, out_dt, off + e, y[e]);
                 }
                 if constexpr (MET) {
 #pragma unroll
                     for (int e = 0; e < V; ++e)
-                        if (val[e]) macc.add(fu[u][e], out_value(d.out_dt, y[e]));
+                        if (val[e]) macc.add(fu[u][e], out_value(out_dt, y[e]));
                 }
             }
         }

@@ -7,13 +7,20 @@
 
 // Every kernel has a batched twin (suffix _b) that serves one pass of many
 // volumes of the same class: it finds its volume and unit in the launch's
-// index table and runs the very same unit function.
+// index table and runs the very same unit function.  The volume index is
+// made a scalar value and the descriptor is read through the constant
+// address space (the table is written before the launch and never during
+// it): its fields then stay in scalar registers across the unit's stores, as
+// for a descriptor passed as a kernel argument, instead of being reloaded
+// with vector loads after every store that might alias the table.
 __device__ __forceinline__ const McVol &mc_resolve(const McBatchSrc &s, uint32_t &u)
 {
+    // the volume and unit are the work-group's own: scalar values
     const uint32_t r = blockIdx.x;
-    const uint32_t j = mc_batch_volume(s.pre, s.n, r);
-    u = r - s.pre[j];
-    return s.vols[s.list[j]];
+    const uint32_t j = __builtin_amdgcn_readfirstlane(mc_batch_volume(s.pre, s.n, r));
+    u = __builtin_amdgcn_readfirstlane(r - s.pre[j]);
+    const uint32_t vi = __builtin_amdgcn_readfirstlane(s.list[j]);
+    return mc::mc_const_desc(s.vols + vi);
 }
 
 template <typename Tin>
