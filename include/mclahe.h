@@ -351,7 +351,7 @@ mclahe_status mclahe_plan_set_batch_tuning(mclahe_plan_t plan, const mclahe_tuni
 /* Autotune the batch tuning of n plans together, on the given buffers
  * (overwritten), by timing whole mclahe_run_batched calls (graph replays):
  * per class of volumes that run the same kernels, the histogram row split
- * (default, 2 or 4 times fewer units) with 1 or 2 LDS replicas, then the
+ * (default, 2 or 4 times fewer units) with 1, 2 or 4 LDS replicas, then the
  * interpolation row chunks per unit.  A result is kept only if it is faster
  * than the default batch tuning when both are timed again, so a tuned batch
  * is never slower than an untuned one; either way the outputs keep their

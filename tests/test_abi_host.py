@@ -543,9 +543,9 @@ def test_batch_tuning_is_kept_apart_from_the_plain_tuning():
     p = Plan((64, 96, 40), (16, 16, 10), 128, 0.02)
     plain = p.tuning()
     b = p.batch_tuning()
-    p.set_batch_tuning(hist_rows_split=1, map_unit_chunks=1, hist_copies=2)
+    p.set_batch_tuning(hist_rows_split=1, map_unit_chunks=1, hist_copies=4)
     nb = p.batch_tuning()
-    assert nb["hist_rows_split"] == 1 and nb["hist_copies"] == 2
+    assert nb["hist_rows_split"] == 1 and nb["hist_copies"] == 4
     assert p.tuning() == plain                   # the plain decomposition did not move
     with pytest.raises(MclaheError):
         p.set_batch_tuning(hist_copies=-1)
