@@ -37,7 +37,7 @@ KSIZE = (32, 32, 16, 8)
 NBINS = 512
 CLIP = 0.02
 PAPER_SIGMA = (0.7, 0.7, 0.9, 1.3)   # pre-smoothing of the photoemission run: momenta, energy, time
-RESIDENT_RATES = (4000.0, 8000.0, 16000.0, 32000.0)   # extra serving rates with inputs already in HBM
+RESIDENT_RATES = (4000.0, 8000.0, 16000.0, 32000.0, 48000.0, 64000.0)   # extra serving rates with inputs already in HBM
 P99_BOUND_MS = 10.0                  # latency bound of the "sustained rate" summary
 
 
