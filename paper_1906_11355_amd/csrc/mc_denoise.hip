@@ -16,6 +16,9 @@
 //     side (reflection never reaches further than r from an output);
 //   - the last two axes, both smoothed, rows of at most 512 samples: one
 //     fused pass through LDS (k_gauss_last2);
+//   - two consecutive smoothed axes before those, both strided, radii up to
+//     8: one pass (k_gauss_pair), the first axis in a register ring per
+//     thread, the second through LDS;
 //   - any other axis (stride S): a thread owns 4 (or 1) adjacent columns and
 //     sweeps a segment of the axis with a ring of 2r + 1 samples in
 //     registers, unrolled by the ring length so that every slot index is a
@@ -479,6 +482,97 @@ __global__ void __launch_bounds__(kT) k_gauss_direct(const T *in, float *out, Co
     }
 }
 
+// Two consecutive strided axes in one pass.  The array is [outer][n0][n1][S]
+// (S > 1 elements after the second axis).  A work-group owns a tile of the
+// second axis, TY outputs plus r1 halo rows on each side (kPairRows rows in
+// all), times kPairCols columns of V adjacent inner elements, and sweeps a
+// segment of the first axis.  Every thread smooths its (row, column) along
+// the first axis with a ring of 2 R0 + 1 inputs in registers, exactly the
+// chain of the one-axis pass; the rows of that plane meet in LDS, and the TY
+// output rows are smoothed along the second axis from there, again with the
+// one-axis chain (tap positions reflected as that pass reflects them).  The
+// result is bit-identical to the two one-axis passes, with one trip through
+// HBM instead of two (the halo rows are read twice, mostly from L2).
+struct Pair {
+    int64_t n0, n1, S;        // first and second axis, inner elements
+    int64_t ccols, nty;       // column groups per row, row tiles
+    int64_t seg, nseg;        // first-axis positions per segment, segments
+    int TY, r1;               // output rows per tile, radius on the second axis
+};
+constexpr int kPairRows = 32, kPairCols = kT / kPairRows;
+
+template <typename T, int V, int R0>
+__global__ void __launch_bounds__(kT) k_gauss_pair(const T *in, float *out, Pair g, Weights W0, Weights W1)
+{
+    constexpr int WN = 2 * R0 + 1;
+    constexpr int CW = kPairCols * V;            // floats per LDS row
+    __shared__ __align__(16) float tl[kPairRows][CW];
+    int64_t b = blockIdx.x;
+    const int64_t cc = b % g.ccols;
+    b /= g.ccols;
+    const int64_t ty = b % g.nty;
+    b /= g.nty;
+    const int64_t sg = b % g.nseg;
+    const int64_t ou = b / g.nseg;
+    const int row = threadIdx.x / kPairCols, cx = threadIdx.x % kPairCols;
+    const int64_t s = (cc * kPairCols + cx) * V;
+    const bool colok = s < g.S;                  // V divides S
+    const int64_t y = ty * g.TY + row - g.r1;    // second-axis position of the row
+    const int64_t pst = g.n1 * g.S;              // first-axis stride
+    const int64_t ibase = ou * g.n0 * pst + refl(y, g.n1) * g.S + s;
+    const bool outrow = colok && row >= g.r1 && row < g.r1 + g.TY && y < g.n1;
+    const int64_t obase = ou * g.n0 * pst + y * g.S + s;
+    const int64_t p0 = sg * g.seg, p1 = std::min(p0 + g.seg, g.n0);
+    float w[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) w[j] = W0.w[j];
+    VecF<V> ring[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int k = 0; k < V; ++k) ring[j].v[k] = 0.f;
+    // slot of first-axis position q: (q - (p0 - R0)) mod WN
+#pragma unroll
+    for (int j = 0; j < 2 * R0; ++j)
+        if (colok) ring[j] = ldv<T, V>(in, ibase + refl(p0 - R0 + j, g.n0) * pst);
+    for (int64_t pb = p0; pb < p1; pb += WN) {
+        VecF<V> nxt[WN];
+#pragma unroll
+        for (int u = 0; u < WN; ++u) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) nxt[u].v[k] = 0.f;
+            if (colok && pb + u < p1) nxt[u] = ldv<T, V>(in, ibase + refl(pb + u + R0, g.n0) * pst);
+        }
+#pragma unroll
+        for (int u = 0; u < WN; ++u) {
+            const int64_t p = pb + u;
+            if (p < p1) {                        // the same for the whole work-group
+                ring[(u + 2 * R0) % WN] = nxt[u];
+                float acc[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) acc[k] = 0.f;
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int k = 0; k < V; ++k) acc[k] = __builtin_fmaf(w[j], ring[(u + j) % WN].v[k], acc[k]);
+#pragma unroll
+                for (int k = 0; k < V; ++k) tl[row][cx * V + k] = acc[k];
+                __syncthreads();
+                if (outrow) {
+                    float o[V];
+#pragma unroll
+                    for (int k = 0; k < V; ++k) o[k] = 0.f;
+                    for (int j = 0; j <= 2 * g.r1; ++j)
+#pragma unroll
+                        for (int k = 0; k < V; ++k) o[k] = __builtin_fmaf(W1.w[j], tl[row - g.r1 + j][cx * V + k], o[k]);
+                    stv<V>(out, obase + p * pst, o);
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // Plain conversion to float (no axis to smooth).
 template <typename T>
 __global__ void __launch_bounds__(kT) k_to_float(const T *in, float *out, int64_t nvox)
@@ -770,6 +864,50 @@ mclahe_status gauss_pass(const T *in, float *out, int64_t nvox, int64_t n, int64
     return MCLAHE_SUCCESS;
 }
 
+// Whether two consecutive strided axes (radii r0, r1) go in one pass.
+bool pair_ok(int r0, int r1) { return r0 >= 1 && r0 <= kRingMax && r1 >= 1 && r1 <= kRingMax; }
+
+template <typename T>
+mclahe_status gauss_pair(const T *in, float *out, int64_t nvox, int64_t n0, int64_t n1, int64_t S, int r0,
+                         const Weights &W0, int r1, const Weights &W1, hipStream_t st)
+{
+    const bool vec = S % 4 == 0 && ((uintptr_t)in % (4 * sizeof(T))) == 0 && ((uintptr_t)out % 16) == 0;
+    const int V = vec ? 4 : 1;
+    Pair g;
+    g.n0 = n0;
+    g.n1 = n1;
+    g.S = S;
+    g.r1 = r1;
+    g.TY = kPairRows - 2 * r1;
+    g.nty = (n1 + g.TY - 1) / g.TY;
+    g.ccols = (S + kPairCols * V - 1) / (kPairCols * V);
+    const int64_t outer = nvox / (n0 * n1 * S);
+    // segments of the first axis: a multiple of the ring length near 64
+    // positions, fewer if the tiles alone do not fill the chip
+    const int WN = 2 * r0 + 1;
+    int64_t seg = ((64 + WN - 1) / WN) * WN;
+    const int64_t tiles = outer * g.nty * g.ccols;
+    while (seg > WN && tiles * ((n0 + seg - 1) / seg) < 4096) seg -= WN;
+    g.seg = std::min<int64_t>(seg, n0);
+    g.nseg = (n0 + g.seg - 1) / g.seg;
+    const int64_t blocks = tiles * g.nseg;
+    if (blocks > 0x7fffffff) return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "volume too large for one pass");
+    const dim3 grid((uint32_t)blocks), blk(kT);
+#define PAIR(RR)                                                                                  \
+    case RR:                                                                                      \
+        if (vec) hipLaunchKernelGGL((k_gauss_pair<T, 4, RR>), grid, blk, 0, st, in, out, g, W0, W1); \
+        else hipLaunchKernelGGL((k_gauss_pair<T, 1, RR>), grid, blk, 0, st, in, out, g, W0, W1);     \
+        break;
+    switch (r0) {
+        PAIR(1) PAIR(2) PAIR(3) PAIR(4) PAIR(5) PAIR(6) PAIR(7) PAIR(8)
+    default: return mc_fail(MCLAHE_ERROR_NOT_SUPPORTED, "pair pass radius");
+    }
+#undef PAIR
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mc_fail(MCLAHE_ERROR_HIP, "gaussian pass launch failed: %s", hipGetErrorString(e));
+    return MCLAHE_SUCCESS;
+}
+
 // Rows of T2 per work-group for the fused last-two-axes pass: about kTile
 // outputs, LDS within 64 KiB.
 int fuse_rows(int n2, int n3, int r2, int r3)
@@ -928,17 +1066,48 @@ mclahe_status mc_gaussian_run(const void *d_in, int in_dtype, int ndim, const in
     }
     // launches: one per smoothed axis, except that the last two axes go in
     // one fused pass when both are smoothed and the rows are short (that
-    // pass also writes the min/max pairs when mm is given)
-    const int L = fuse ? P - 1 : P;
+    // pass also writes the min/max pairs when mm is given), and that two
+    // consecutive smoothed axes before them, both strided, share one pass
+    // (kind: 0 one axis, 1 the pair a, a + 1, 2 the last two axes)
+    std::vector<std::pair<int, int>> groups;
+    {
+        const int Pn = fuse ? P - 2 : P;
+        for (int k = 0; k < Pn;) {
+            const int a = axes[k];
+            if (k + 1 < Pn && axes[k + 1] == a + 1 && a + 1 < ndim - 1 &&
+                pair_ok(gauss_radius(sigma[a], truncate), gauss_radius(sigma[a + 1], truncate))) {
+                groups.push_back({a, 1});
+                k += 2;
+            } else {
+                groups.push_back({a, 0});
+                ++k;
+            }
+        }
+        if (fuse) groups.push_back({ndim - 2, 2});
+    }
+    const int L = (int)groups.size();
     float *tmp = (float *)d_workspace;
     const float *src = nullptr;
     for (int k = 0; k < L; ++k) {
-        const int a = axes[k];
+        const int a = groups[k].first, kind = groups[k].second;
         float *dst = ((L - 1 - k) % 2 == 0) ? d_out : tmp;   // the last launch lands in d_out
         Weights W;
         int r;
         gauss_weights(sigma[a], truncate, W, r);
-        if (fuse && k == L - 1) {
+        if (kind == 1) {
+            Weights W1;
+            int r1;
+            gauss_weights(sigma[a + 1], truncate, W1, r1);
+            int64_t S = 1;
+            for (int i = a + 2; i < ndim; ++i) S *= shape[i];
+            if (k == 0) {
+                if (in_dtype == MCLAHE_U8) s = gauss_pair<uint8_t>((const uint8_t *)d_in, dst, nvox, shape[a], shape[a + 1], S, r, W, r1, W1, st);
+                else if (in_dtype == MCLAHE_U16) s = gauss_pair<uint16_t>((const uint16_t *)d_in, dst, nvox, shape[a], shape[a + 1], S, r, W, r1, W1, st);
+                else s = gauss_pair<float>((const float *)d_in, dst, nvox, shape[a], shape[a + 1], S, r, W, r1, W1, st);
+            } else {
+                s = gauss_pair<float>(src, dst, nvox, shape[a], shape[a + 1], S, r, W, r1, W1, st);
+            }
+        } else if (kind == 2) {
             Weights W3;
             int r3;
             gauss_weights(sigma[ndim - 1], truncate, W3, r3);

@@ -71,6 +71,11 @@ GAUSS_CASES = [
     ((20, 500), (16.0, 16.0), np.float32),             # radius 64: too wide to fuse the last two axes
     ((3, 2, 512), (0.0, 1.4, 0.6), np.uint8),          # fused last two axes, longest fused rows, first pass
     ((4, 9, 1), (0.8, 2.2, 3.0), np.float32),          # fused, rows of one sample, generic radii
+    # two leading strided axes in one pass
+    ((3, 40, 30, 6), (0.9, 1.3, 0.0, 0.7), np.float32),  # radii 4 and 5, two row tiles, wide vectors
+    ((70, 3, 5, 4), (0.7, 1.3, 0.9, 0.0), np.uint8),     # second axis shorter than its radius, first pass
+    ((3, 11, 9, 2, 5), (0.0, 0.7, 0.9, 0.0, 1.1), np.float32),  # pair after an outer axis, scalar columns
+    ((130, 27, 2, 8), (0.4, 0.7, 0.0, 0.0), np.uint16),  # radii 2 and 3, segments of the first axis
 ]
 
 
@@ -89,6 +94,10 @@ def test_gaussian_misaligned(in_off, out_off):
     x = _data(rng, (12, 16, 20), np.uint16 if in_off == 2 else np.float32)
     np.testing.assert_array_equal(gpu_gaussian(x, (0.9, 0.7, 1.3), in_off=in_off, out_off=out_off),
                                   DN.gaussian(x, (0.9, 0.7, 1.3)))
+    # the two-axis pass with unaligned buffers (single-element columns)
+    x4 = _data(rng, (8, 9, 6, 8), np.uint16 if in_off == 2 else np.float32)
+    np.testing.assert_array_equal(gpu_gaussian(x4, (0.7, 0.7, 0.9, 1.3), in_off=in_off, out_off=out_off),
+                                  DN.gaussian(x4, (0.7, 0.7, 0.9, 1.3)))
 
 
 @pytest.mark.timeout(300)
