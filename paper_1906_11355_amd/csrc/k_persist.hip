@@ -41,11 +41,11 @@ struct DevAtomics {
 
 // Each kind of unit is its own (not inlined) function, so that the kernel
 // needs the registers of the heaviest one, not of all of them at once.
-template <typename Tin, bool AHR, bool RO>
+template <typename Tin, bool AHR, bool RO, bool VAL = false>
 __device__ __noinline__ void pu_hist(const McVol &v, uint32_t u, char *smem)
 {
     // wavefront aggregation changes no count: the plain update serves all
-    mc::hist_unit_dispatch<Tin, AHR, RO, 0>(v, u, smem);
+    mc::hist_unit_dispatch<Tin, AHR, RO, 0, VAL>(v, u, smem);
 }
 template <typename Tin>
 __device__ __noinline__ void pu_range(const McVol &v, uint32_t u, char *smem)
@@ -72,6 +72,13 @@ __device__ void persist_unit(const McVol &v, uint32_t ph, uint32_t u, char *smem
         if (ahr) pu_hist<Tin, true, true>(v, u, smem);
         else pu_range<Tin>(v, u, smem);
     } else if (ph == 1) {
+        if constexpr (sizeof(Tin) == 1) {
+            if (v.vhist) {   // uint8 counted per value
+                if (ahr) pu_hist<Tin, true, false, true>(v, u, smem);
+                else pu_hist<Tin, false, false, true>(v, u, smem);
+                return;
+            }
+        }
         if (ahr) pu_hist<Tin, true, false>(v, u, smem);
         else pu_hist<Tin, false, false>(v, u, smem);
     } else if (ph == 2) {

@@ -150,6 +150,9 @@ struct McVol {
                               // of the interpolation units (0 for whole volumes)
     int32_t ntst;             // 1: output row segments are whole 64-byte blocks
                               //    -> streaming (non-temporal) stores
+    int32_t vhist;            // 1: uint8 input counted per value (256 slots per
+                              //    kernel, no range pass); the clip pass takes
+                              //    the range and re-bins the values
     int64_t hCols;            // kernel columns (prod of n_i, i < D-1)
     uint32_t n_hist_wu;       // hCols * hS * hCr
     uint32_t n_range_wu;      // GHR min/max blocks (0 if a user range is given)
@@ -206,7 +209,7 @@ struct McBatchSrc {
 // Units of pass ph of a volume: 0 range, 1 histogram, 2 clip/CDF, 3 map.
 MC_HD uint32_t mc_phase_units(const McVol &v, int ph)
 {
-    return ph == 0 ? (v.mode == MC_AHR ? v.n_hist_wu : v.n_range_wu)
+    return ph == 0 ? (v.vhist ? 0u : v.mode == MC_AHR ? v.n_hist_wu : v.n_range_wu)
          : ph == 1 ? v.n_hist_wu : ph == 2 ? v.n_clip_wu : v.n_map_wu;
 }
 

@@ -527,6 +527,14 @@ __device__ __forceinline__ void build_memb(const McVol &d, int kA, int kB, int x
                                            int x0, Memb<V> &m)
 {
     const McAxis &a = d.ax[d.D - 1];
+    // While kernels are at least V wide, the padded positions of the V
+    // elements fall in the kernel of the first one or the next: the boxes of
+    // those two and of the two fold kernels serve every element (four boxes
+    // per thread instead of up to three per element).
+    const bool wide = a.b >= V;
+    const int kd0 = (x0 + a.p0) / a.b;
+    const McBox bfirst = mc_kernel_box(a, 0), blast = mc_kernel_box(a, a.n - 1);
+    const McBox bd0 = mc_kernel_box(a, kd0), bd1 = mc_kernel_box(a, kd0 + 1);
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         const int x = x0 + e;
@@ -534,16 +542,26 @@ __device__ __forceinline__ void build_memb(const McVol &d, int kA, int kB, int x
         m.w1[e] = 0;
         m.extra[e] = 0;
         if (x < xs || x >= xe) continue;
-        const int kd = (x + a.p0) / a.b;
+        int kd;
+        McBox bd;
+        if (wide) {
+            const bool up = x + a.p0 >= (kd0 + 1) * a.b;
+            kd = up ? kd0 + 1 : kd0;
+            bd = up ? bd1 : bd0;
+        } else {
+            kd = (x + a.p0) / a.b;
+            bd = mc_kernel_box(a, kd);
+        }
         int cand[3] = {x < a.p0 ? 0 : -1, kd, x >= a.s - a.p1 ? a.n - 1 : -1};
         if (cand[0] == kd) cand[0] = -1;          // the same kernel counts once
         if (cand[2] == kd) cand[2] = -1;
+        const McBox *box[3] = {&bfirst, &bd, &blast};
         int found = 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int k = cand[c];
             if (k < kA || k >= kB) continue;
-            const int w = mc_mult(mc_kernel_box(a, k), x);
+            const int w = mc_mult(*box[c], x);
             if (!w) continue;
             if (found == 0) {
                 m.s1[e] = k - kA;
@@ -622,10 +640,15 @@ __device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int
     if (key >= 0) atomicAdd(&h[key + cp], val);
 }
 
-template <typename Tin, int V, bool AHR, bool RANGE_ONLY, int PEEL>
+// VAL (uint8 input): the slots count values (256 per kernel) instead of
+// bins; no range is needed here (the clip pass takes it and re-bins), and
+// under a global range each unit also writes the smallest and largest value
+// it counted.
+template <typename Tin, int V, bool AHR, bool RANGE_ONLY, int PEEL, bool VAL = false>
 __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
 {
-    const int D = d.D, nb = d.nb;
+    static_assert(!VAL || (sizeof(Tin) == 1 && !RANGE_ONLY), "value slots: uint8 counting only");
+    const int D = d.D, nb = VAL ? 256 : d.nb;
     HistLds L = hist_lds(d, smem);
     int64_t col;
     int seg, chunk;
@@ -651,7 +674,9 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     const float nbf = (float)nb;
     const int nbm1 = nb - 1;
     if constexpr (!RANGE_ONLY) {
-        if constexpr (!AHR) {
+        if constexpr (VAL) {
+            // values are counted as they are
+        } else if constexpr (!AHR) {
             float ghi;
             ghr_range(d, L.red, glo, ghi, gsc);
             if (wu == 0 && threadIdx.x == 0) {
@@ -727,7 +752,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     for (int e = 0; e < V; ++e) {
         lo1[e] = glo;
         sc1[e] = gsc;
-        if constexpr (AHR && !RANGE_ONLY) {
+        if constexpr (AHR && !RANGE_ONLY && !VAL) {
             if (m.s1[e] >= 0) {
                 lo1[e] = L.slot_lo[m.s1[e]];
                 sc1[e] = L.slot_sc[m.s1[e]];
@@ -796,7 +821,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
             if constexpr (!RANGE_ONLY && PEEL == 0) {
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
-                    const uint32_t b = (uint32_t)bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
+                    const uint32_t b = VAL ? (uint32_t)f[e] : (uint32_t)bin_of(f[e], lo1[e], sc1[e], nbf, nbm1);
                     atomicAdd((uint32_t *)((char *)L.h + ((b << bsh) + hoff[e])), __umul24(wrow, w1[e]));
                 }
             }
@@ -810,7 +835,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                     key[e] = -1;
                     wk[e] = wrow * m.w1[e];
                     if (m.s1[e] >= 0) {
-                        key[e] = m.s1[e] * SS + bin_of(f[e], lo1[e], sc1[e], nbf, nbm1) * R;
+                        key[e] = m.s1[e] * SS + (VAL ? (int)f[e] : bin_of(f[e], lo1[e], sc1[e], nbf, nbm1)) * R;
                     }
                 }
             }
@@ -837,9 +862,10 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
                         while (ex) {
                             const int s = (int)(ex & 0xff) - 1;
                             const uint32_t w = (ex >> 8) & 0xff;
-                            const float lo = AHR ? L.slot_lo[s] : glo;
-                            const float sc = AHR ? L.slot_sc[s] : gsc;
-                            atomicAdd(&L.h[s * SS + bin_of(f[e], lo, sc, nbf, nbm1) * R + cp], wrow * w);
+                            const float lo = AHR && !VAL ? L.slot_lo[s] : glo;
+                            const float sc = AHR && !VAL ? L.slot_sc[s] : gsc;
+                            const int b = VAL ? (int)f[e] : bin_of(f[e], lo, sc, nbf, nbm1);
+                            atomicAdd(&L.h[s * SS + b * R + cp], wrow * w);
                             ex >>= 16;
                         }
                     }
@@ -899,23 +925,49 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         // flush: partial histogram of every slot (replicas summed)
         uint32_t *dst = d.part + (int64_t)wu * d.hG * nb;
         const int tot = d.hG * nb;
+        int vmin = 256, vmax = -1;   // VAL: smallest and largest value counted
         for (int i = threadIdx.x; i < tot; i += MC_T) {
             uint32_t s = 0;
             if (i < nslot * nb) {
                 const int sl = i / nb, b = i - sl * nb;
                 for (int c = 0; c < R; ++c) s += L.h[sl * SS + b * R + c];
+                if (VAL && s) {
+                    vmin = mc_min(vmin, b);
+                    vmax = mc_max(vmax, b);
+                }
             }
             dst[i] = s;
+        }
+        if constexpr (VAL && !AHR) {
+            // the unit's (min, max) value, for the global range of the clip
+            // pass (+inf/-inf when the unit counted nothing)
+            int *ri = (int *)L.red;
+            if (threadIdx.x == 0) {
+                ri[0] = 256;
+                ri[1] = -1;
+            }
+            __syncthreads();
+            if (vmax >= 0) {
+                atomicMin(&ri[0], vmin);
+                atomicMax(&ri[1], vmax);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                d.rpart[2 * (int64_t)wu] = ri[1] >= 0 ? (float)ri[0] : INFINITY;
+                d.rpart[2 * (int64_t)wu + 1] = ri[1] >= 0 ? (float)ri[1] : -INFINITY;
+            }
         }
     }
 }
 
-template <typename Tin, bool AHR, bool RANGE_ONLY, int PEEL>
+// VAL: value slots (uint8 input with d.vhist set), a kernel of its own so
+// that each variant gets the registers it needs
+template <typename Tin, bool AHR, bool RANGE_ONLY, int PEEL, bool VAL = false>
 __device__ void hist_unit_dispatch(const McVol &d, uint32_t wu, char *smem)
 {
     constexpr int VM = mc_vec_elems((int)sizeof(Tin));
-    if (d.vec == VM) hist_unit_v<Tin, VM, AHR, RANGE_ONLY, PEEL>(d, wu, smem);
-    else hist_unit_v<Tin, 1, AHR, RANGE_ONLY, PEEL>(d, wu, smem);
+    if (d.vec == VM) hist_unit_v<Tin, VM, AHR, RANGE_ONLY, PEEL, VAL>(d, wu, smem);
+    else hist_unit_v<Tin, 1, AHR, RANGE_ONLY, PEEL, VAL>(d, wu, smem);
 }
 
 // ----------------------------------------------------- clip + CDF + LUT --
@@ -989,10 +1041,109 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
     uint32_t *hk = d.hist + (int64_t)k * nb;
     unsigned long long smin = 0, exc = 0;
     const int np = nsg * d.hCr;   // partials of this kernel
+    uint32_t *hs = (uint32_t *)(smem + MC_T * 8);   // counted values re-binned (vhist)
+    if (d.vhist) {
+        // uint8 input counted per value: thread v sums the kernel's count of
+        // value v, the range is taken (per kernel, the caller's, or the
+        // smallest and largest value any unit counted), and the values are
+        // re-binned exactly as the histogram pass bins a voxel of that value.
+        // The first range partials and the counts are all in flight before
+        // either is reduced.
+        const int v = threadIdx.x;   // MC_T == 256 values
+        const bool gpart = d.mode == MC_GHR && !d.has_user_range;
+        float2 rv[MC_STAGE];
+#pragma unroll
+        for (int q = 0; q < MC_STAGE; ++q) {
+            const uint32_t i = (uint32_t)threadIdx.x + (uint32_t)q * MC_T;
+            rv[q] = gpart && i < d.n_hist_wu ? make_float2(d.rpart[2 * (int64_t)i], d.rpart[2 * (int64_t)i + 1])
+                                             : make_float2(INFINITY, -INFINITY);
+        }
+        uint32_t cnt = 0;
+        for (int p0 = 0; p0 < np; p0 += MC_STAGE) {
+            uint32_t pv[MC_STAGE];
+#pragma unroll
+            for (int q = 0; q < MC_STAGE; ++q) {
+                const int pi = p0 + q;
+                pv[q] = 0u;
+                if (pi < np) {
+                    const int g = pi / d.hCr, c = pi - g * d.hCr;
+                    const int64_t u = (col * d.hS + sg0 + g) * d.hCr + c;
+                    pv[q] = d.part[(u * d.hG + sl) * 256 + v];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < MC_STAGE; ++q) cnt += pv[q];
+        }
+        float lo, hi;
+        if (d.mode == MC_GHR && d.has_user_range) {
+            lo = d.user_lo;
+            hi = d.user_hi;
+        } else {
+            // order-preserving integers, reduced by wave shuffles, then
+            // across the MC_T / 64 waves
+            int mn = 0x7fffffff, mx = (int)0x80000000;
+            if (d.mode == MC_AHR) {
+                if (cnt) mn = mx = f2o((float)v);
+            } else {
+#pragma unroll
+                for (int q = 0; q < MC_STAGE; ++q) {
+                    mn = mc_min(mn, f2o(rv[q].x));
+                    mx = mc_max(mx, f2o(rv[q].y));
+                }
+                for (uint32_t i0 = threadIdx.x + MC_STAGE * MC_T; i0 < d.n_hist_wu; i0 += MC_STAGE * MC_T) {
+#pragma unroll
+                    for (int q = 0; q < MC_STAGE; ++q) {
+                        const uint32_t i = i0 + (uint32_t)q * MC_T;
+                        rv[q] = i < d.n_hist_wu ? make_float2(d.rpart[2 * (int64_t)i], d.rpart[2 * (int64_t)i + 1])
+                                                : make_float2(INFINITY, -INFINITY);
+                    }
+#pragma unroll
+                    for (int q = 0; q < MC_STAGE; ++q) {
+                        mn = mc_min(mn, f2o(rv[q].x));
+                        mx = mc_max(mx, f2o(rv[q].y));
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                mn = mc_min(mn, __shfl_xor(mn, o));
+                mx = mc_max(mx, __shfl_xor(mx, o));
+            }
+            int *ri = (int *)smem;
+            if (lane_id() == 0) {
+                ri[2 * (threadIdx.x >> 6)] = mn;
+                ri[2 * (threadIdx.x >> 6) + 1] = mx;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < MC_T / 64; ++w) {
+                mn = mc_min(mn, ri[2 * w]);
+                mx = mc_max(mx, ri[2 * w + 1]);
+            }
+            lo = o2f(mn);
+            hi = o2f(mx);
+        }
+        const float sc = range_scale(nb, lo, hi);
+        if (threadIdx.x == 0) {
+            if (d.mode == MC_AHR) {
+                d.range[2 * (int64_t)k] = lo;
+                d.range[2 * (int64_t)k + 1] = hi;
+                d.scale[k] = sc;
+            } else if (k == 0) {
+                d.range[0] = lo;
+                d.range[1] = hi;
+                d.scale[0] = sc;
+            }
+        }
+        for (int i = threadIdx.x; i < nb; i += MC_T) hs[i] = 0u;
+        __syncthreads();
+        if (cnt) atomicAdd(&hs[bin_of((float)v, lo, sc, (float)nb, nb - 1)], cnt);
+        __syncthreads();
+    }
     for (int j = j0; j < j1; ++j) {
         // MC_STAGE partials in flight at a time (integer sums: exact in any order)
-        uint32_t h = 0;
-        for (int p0 = 0; p0 < np; p0 += MC_STAGE) {
+        uint32_t h = d.vhist ? hs[j] : 0u;
+        for (int p0 = 0; p0 < (d.vhist ? 0 : np); p0 += MC_STAGE) {
             uint32_t pv[MC_STAGE];
 #pragma unroll
             for (int q = 0; q < MC_STAGE; ++q) {

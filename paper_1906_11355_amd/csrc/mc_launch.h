@@ -20,7 +20,7 @@ struct KPair {
 KPair mc_pick_range_u8();
 KPair mc_pick_range_u16();
 KPair mc_pick_range_f32();
-KPair mc_pick_hist_u8(bool ahr, bool ro, int peel);
+KPair mc_pick_hist_u8(bool ahr, bool ro, int peel, bool val);   // val: per-value slots
 KPair mc_pick_hist_u16(bool ahr, bool ro, int peel);
 KPair mc_pick_hist_f32(bool ahr, bool ro, int peel);
 KPair mc_pick_map_u8(int D, bool ahr, int path);

@@ -38,19 +38,19 @@ __global__ __launch_bounds__(MC_T) void k_range_ghr_b(McBatchSrc s)
     mc::range_ghr_unit<Tin>(d, u, smem);
 }
 
-template <typename Tin, bool AHR, bool RO, int PEEL>
+template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
 __global__ __launch_bounds__(MC_T) void k_hist(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
-    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL>(d, blockIdx.x, smem);
+    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, blockIdx.x, smem);
 }
-template <typename Tin, bool AHR, bool RO, int PEEL>
+template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
 __global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
     const McVol &d = mc_resolve(s, u);
-    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL>(d, u, smem);
+    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, u, smem);
 }
 
 template <typename Tin, int D, bool AHR>
@@ -117,12 +117,21 @@ static KFn pick_map_met_t2(int D, bool ahr, int path)
     return ahr ? pick_map_met_t<Tin, true>(D, path) : pick_map_met_t<Tin, false>(D, path);
 }
 
-template <typename Tin, bool AHR, bool RO, int PEEL>
-static KPair hist_pair() { return KPair{(KFn)k_hist<Tin, AHR, RO, PEEL>, (KFnB)k_hist_b<Tin, AHR, RO, PEEL>, MC_T}; }
+template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
+static KPair hist_pair()
+{
+    return KPair{(KFn)k_hist<Tin, AHR, RO, PEEL, VAL>, (KFnB)k_hist_b<Tin, AHR, RO, PEEL, VAL>, MC_T};
+}
 
 template <typename Tin>
-static KPair pick_hist_t(bool ahr, bool ro, int peel)
+static KPair pick_hist_t(bool ahr, bool ro, int peel, bool val = false)
 {
+    if constexpr (sizeof(Tin) == 1) {
+        if (val && !ro) {
+            if (ahr) return peel == 0 ? hist_pair<Tin, true, false, 0, true>() : hist_pair<Tin, true, false, 1, true>();
+            return peel == 0 ? hist_pair<Tin, false, false, 0, true>() : hist_pair<Tin, false, false, 1, true>();
+        }
+    }
     if (ro) return hist_pair<Tin, true, true, 0>();
     if (ahr) return peel == 0 ? hist_pair<Tin, true, false, 0>() : hist_pair<Tin, true, false, 1>();
     return peel == 0 ? hist_pair<Tin, false, false, 0>() : hist_pair<Tin, false, false, 1>();

@@ -162,7 +162,7 @@ static int seg_chunks(int xs, int xe, int V) { return (xe + V - 1) / V - xs / V;
 // a global range, interpolation units run row chunks on one staging of
 // their LUTs: by default as many as leave map_units units for the volume.
 static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t, int64_t unit_vox,
-                                 int64_t min_map_cols, int64_t map_units, bool vector, McVol &v)
+                                 int64_t min_map_cols, int64_t map_units, bool vector, bool spread, McVol &v)
 {
     memset(&v, 0, sizeof v);
     const int D = p->D;
@@ -200,11 +200,17 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
     // mix 1.100 -> 1.058 ms); more did not pay for zeroing and summing them
     int R = t.hist_copies > 0 ? t.hist_copies : 2;
     if (R != 1 && R != 2 && R != 4 && R != 8) return fail(MCLAHE_ERROR_INVALID_VALUE, "hist_copies must be 1, 2, 4 or 8");
+    // uint8 input is counted per value (256 slots per kernel) and re-binned
+    // by the clip pass, which also takes the range: no range pass.  The slot
+    // sizes below fit both that and a bin histogram (the out-of-core run
+    // counts bins with the same units).
+    v.vhist = p->in_dt == MC_U8 ? 1 : 0;
+    const int nbs = v.vhist ? std::max(p->nb, 256) : p->nb;
     const size_t hdr = hist_lds_header();
-    while (R > 1 && hdr + (size_t)mc_hist_slot_stride(p->nb, R) * 4 > MC_LDS_BUDGET) R /= 2;
-    if (hdr + (size_t)mc_hist_slot_stride(p->nb, 1) * 4 > MC_LDS_BUDGET)
+    while (R > 1 && hdr + (size_t)mc_hist_slot_stride(nbs, R) * 4 > MC_LDS_BUDGET) R /= 2;
+    if (hdr + (size_t)mc_hist_slot_stride(nbs, 1) * 4 > MC_LDS_BUDGET)
         return fail(MCLAHE_ERROR_NOT_SUPPORTED, "n_bins=%d needs more LDS than a work-group may use", p->nb);
-    int Gmax = (int)std::min<size_t>(64, (MC_LDS_BUDGET - hdr) / ((size_t)mc_hist_slot_stride(p->nb, R) * 4));
+    int Gmax = (int)std::min<size_t>(64, (MC_LDS_BUDGET - hdr) / ((size_t)mc_hist_slot_stride(nbs, R) * 4));
     Gmax = std::max(1, std::min(Gmax, al.n));
     int G = 0;
     for (int g = Gmax; g >= 1; --g) {
@@ -242,9 +248,7 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
             if (ok) break;
         }
     }
-    v.hG = G;
     v.hP = P;
-    v.hS = P == 1 ? (al.n + G - 1) / G : al.n * P;
     v.hR = R;
     // hist_peel: 0 = default (no aggregation), k >= 1 = k - 1 rounds
     v.hPeel = t.hist_peel > 1 ? 1 : 0;   // one aggregation round (a second only spilled)
@@ -264,34 +268,62 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
     // default row split: ~2048 units, but no unit under ~16K voxels (the
     // fixed cost of a unit, zeroing and flushing its LDS histograms, then
     // dominates; measured on the 2D 512x512 and 3D 256x256x128 workloads)
-    int64_t seglen = 0;
-    for (int j = 0; j < v.hS; ++j) {
-        int kA, kB, xs, xe;
-        if (P == 1) {
-            kA = j * G;
-            kB = std::min(kA + G, al.n);
-            seg_extent(al, kA, kB, xs, xe);
-        } else {
-            McBox bx = mc_kernel_box(al, j / P);
-            xs = bx.lo;
-            xe = bx.hi;
-            seglen = std::max<int64_t>(seglen, ((int64_t)(xe - xs) + P - 1) / P);
-            continue;
+    auto split_for = [&](int g, bool tuned, int64_t &segs, int64_t &cr) {
+        segs = P == 1 ? (al.n + g - 1) / g : (int64_t)al.n * P;
+        int64_t seglen = 0;
+        for (int j = 0; j < segs; ++j) {
+            int xs, xe;
+            if (P == 1) {
+                seg_extent(al, j * g, std::min(j * g + g, al.n), xs, xe);
+                seglen = std::max<int64_t>(seglen, (int64_t)(xe - xs));
+            } else {
+                const McBox bx = mc_kernel_box(al, j / P);
+                seglen = std::max<int64_t>(seglen, ((int64_t)(bx.hi - bx.lo) + P - 1) / P);
+            }
         }
-        seglen = std::max<int64_t>(seglen, (int64_t)(xe - xs));
+        const int64_t cr_units = (2048 + v.hCols * segs - 1) / (v.hCols * segs);
+        const int64_t cr_work = std::max<int64_t>(1, rmax_h * seglen / unit_vox);
+        cr = tuned && t.hist_rows_split > 0 ? t.hist_rows_split : std::min(cr_units, cr_work);
+        cr = std::max<int64_t>(cr, crmin_h);
+        cr = std::min<int64_t>(cr, std::max<int64_t>(rmax_h, crmin_h));
+    };
+    // A volume alone takes fewer kernels per segment when the widest segments
+    // leave fewer units than compute units: a unit then zeroes and flushes
+    // fewer histograms and its work-group has fewer rows to walk, and the
+    // units spread over the chip (2D 512x512 uint8, 9 kernels per row:
+    // segments of 9 kernels in 18 units, 20.6 us, against single kernels in
+    // 81 units, 15.6 us).  The largest segment that still gives a unit per
+    // compute unit is kept, else the one giving the most units (counted with
+    // the default row split, so that the choice does not depend on tuning).
+    if (spread && P == 1) {
+        int best = G;
+        int64_t best_units = -1;
+        for (int g = G; g >= 1; --g) {
+            int64_t segs, cr;
+            split_for(g, false, segs, cr);
+            const int64_t u = v.hCols * segs * cr;
+            if (u >= MC_NUM_CU) {
+                best = g;
+                break;
+            }
+            if (u > best_units) {
+                best_units = u;
+                best = g;
+            }
+        }
+        G = best;
     }
-    const int64_t cr_units = (2048 + v.hCols * v.hS - 1) / (v.hCols * v.hS);
-    const int64_t cr_work = std::max<int64_t>(1, rmax_h * seglen / unit_vox);
-    int64_t cr = t.hist_rows_split > 0 ? t.hist_rows_split : std::min(cr_units, cr_work);
-    cr = std::max<int64_t>(cr, crmin_h);
-    cr = std::min<int64_t>(cr, std::max<int64_t>(rmax_h, crmin_h));
+    v.hG = G;
+    int64_t segs = 0, cr = 0;
+    split_for(G, true, segs, cr);
+    v.hS = (int)segs;
     if (cr > (1 << 20)) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "row split too large");
     v.hCr = (int)cr;
     const int64_t nhu = v.hCols * v.hS * v.hCr;
     if (nhu >= (int64_t)1 << 31) return fail(MCLAHE_ERROR_NOT_SUPPORTED, "too many histogram units");
     v.n_hist_wu = (uint32_t)nhu;
     if (p->mode == MC_GHR) {
-        v.n_range_wu = p->has_ur ? 0 : (uint32_t)std::min<int64_t>(1024, std::max<int64_t>(1, p->nvox / (MC_T * 64)));
+        v.n_range_wu = p->has_ur || v.vhist ? 0 : (uint32_t)std::min<int64_t>(1024, std::max<int64_t>(1, p->nvox / (MC_T * 64)));
     } else {
         v.n_range_wu = 0;
     }
@@ -412,20 +444,24 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
 
 // Words of the per-unit partial histograms and floats of the range partials
 // a decomposition writes.
-static uint64_t part_words(const McVol &v) { return (uint64_t)v.n_hist_wu * v.hG * v.nb; }
+static uint64_t part_words(const McVol &v)
+{
+    return (uint64_t)v.n_hist_wu * v.hG * (uint64_t)(v.vhist ? std::max(v.nb, 256) : v.nb);
+}
 static uint64_t rpart_floats(const McVol &v)
 {
+    if (v.vhist) return (uint64_t)v.n_hist_wu * 2;   // GHR: one (min, max) per unit
     return v.mode == MC_GHR ? (uint64_t)std::max<uint32_t>(v.n_range_wu, 1) * 2 : (uint64_t)v.n_hist_wu * v.hG * 2;
 }
 
 // LDS bytes of pass ph (0 range, 1 histogram, 2 clip, 3 map) under v.
 static size_t pass_lds(const mclahe_plan_s *p, const McVol &v, int ph)
 {
-    const size_t hist = hist_lds_header() + (size_t)v.hG * mc_hist_slot_stride(v.nb, v.hR) * 4;
+    const size_t hist = hist_lds_header() + (size_t)v.hG * mc_hist_slot_stride(v.vhist ? 256 : v.nb, v.hR) * 4;
     switch (ph) {
     case 0: return p->mode == MC_AHR ? hist : 2 * MC_T * 4;
     case 1: return hist;
-    case 2: return MC_T * 8;
+    case 2: return MC_T * 8 + (v.vhist ? (size_t)v.nb * 4 : 0);   // + the re-binned histogram
     default: return v.path == 0 ? map_otab_bytes(p->D) + map_lut_bytes(p, v.mG) : 0;
     }
 }
@@ -437,10 +473,10 @@ static mclahe_status derive(mclahe_plan_s *p)
 {
     mclahe_status s;
     const int64_t bmu = std::max<int64_t>(1, p->nvox / kMapUnitVoxBatch);
-    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, bmu, true, p->bv))) return s;
-    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, bmu, false, p->bv1))) return s;
-    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, 1024, true, p->v))) return s;
-    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, 1024, false, p->v1))) return s;
+    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, bmu, true, false, p->bv))) return s;
+    if ((s = derive_core(p, p->btune, kUnitVoxBatch, 1, bmu, false, false, p->bv1))) return s;
+    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, 1024, true, true, p->v))) return s;
+    if ((s = derive_core(p, p->tune, kUnitVoxPlain, kMinMapCols, 1024, false, true, p->v1))) return s;
     uint64_t pw = 0, rf = 0;
     for (const McVol *d : {&p->v, &p->v1, &p->bv, &p->bv1}) {
         pw = std::max(pw, part_words(*d));
@@ -526,11 +562,11 @@ static KPair phase_kernels(const mclahe_plan_s *p, const McVol &v, int ph, size_
     switch (ph) {
     case 0:
         if (ahr)
-            return dt == MC_U8 ? mc_pick_hist_u8(true, true, 0)
+            return dt == MC_U8 ? mc_pick_hist_u8(true, true, 0, false)
                  : dt == MC_U16 ? mc_pick_hist_u16(true, true, 0) : mc_pick_hist_f32(true, true, 0);
         return dt == MC_U8 ? mc_pick_range_u8() : dt == MC_U16 ? mc_pick_range_u16() : mc_pick_range_f32();
     case 1:
-        return dt == MC_U8 ? mc_pick_hist_u8(ahr, false, v.hPeel)
+        return dt == MC_U8 ? mc_pick_hist_u8(ahr, false, v.hPeel, v.vhist != 0)
              : dt == MC_U16 ? mc_pick_hist_u16(ahr, false, v.hPeel) : mc_pick_hist_f32(ahr, false, v.hPeel);
     case 2:
         return KPair{(KFn)k_clip, (KFnB)k_clip_b, MC_T};
@@ -818,6 +854,7 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
         const char *sin = cur - (size_t)base * row_in;
         char *sout = outbuf[Y] - (size_t)g.mr0[j] * row_out;
         McVol v = vec_aligned(p, sin, sout) ? p->v : p->v1;
+        v.vhist = 0;   // the global range is known before the slabs: bin histograms
         v.wk0 = kA;
         v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
         v.n_clip_wu = (uint32_t)((int64_t)nl * g.layer_kernels);
