@@ -117,7 +117,9 @@ __device__ void persist_unit(const McVol &v, uint32_t ph, uint32_t u, char *smem
 // two nested loops: the other lanes went back to the barrier without the
 // outer loop in which thread 0 takes tickets, so a work-group re-ran its
 // unit forever and the launch never ended.
-__global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s)
+// vols: the descriptors again, as a restrict parameter (read with scalar
+// loads; the table is not written during the launch)
+__global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s, const McVol *__restrict__ vols)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t info[4];
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s)
             // the producers' writes (released before their counters moved);
             // the range pass reads only the input
             if (ph > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const McVol &v = s.vols[vi];
+            const McVol &v = vols[vi];
             const uint32_t u = uw & 0x7fffffffu;
             if (v.in_dt == MC_U8) persist_unit<uint8_t>(v, ph, u, smem);
             else if (v.in_dt == MC_U16) persist_unit<uint16_t>(v, ph, u, smem);

@@ -12,7 +12,19 @@
 #define MC_HD inline
 #endif
 
+// Device code addresses the volume's buffers in the global address space
+// (the host sees plain pointers; the layout is the same).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MC_GLOBAL __attribute__((address_space(1)))
+#else
+#define MC_GLOBAL
+#endif
+
 #define MC_MAXD 8          // dimensions supported
+
+// A device buffer pointer as the descriptor holds it.
+template <typename T>
+MC_HD MC_GLOBAL T *mc_gp(T *p) { return (MC_GLOBAL T *)p; }
 #define MC_T 256           // threads per work-group (4 wavefronts of 64)
 #define MC_MAP_T 512       // threads per work-group of the LDS-staged map with
                            // a global range (its LDS bounds the units per CU:
@@ -164,18 +176,19 @@ struct McVol {
     int64_t mCols;            // cell columns (prod of n_i - 1, i < D-1)
     uint32_t n_map_wu;        // mCols * mS * mU
     uint32_t n_clip_wu;       // = nker
-    // ---- buffers -------------------------------------------------------------
-    const void *in;
-    void *out;
-    uint32_t *part;           // [n_hist_wu][hG][nb]   partial histograms
-    float *rpart;             // GHR: [n_range_wu][2]; AHR: [n_hist_wu][hG][2]
-    uint32_t *hist;           // [nker][nb]
-    unsigned long long *clipped;  // [nker][nb]
-    float *lut;               // [nker][nb]
-    float *range;             // GHR: [2]; AHR: [nker][2]
-    float *scale;             // GHR: [1]; AHR: [nker]
-    McMetPart *met;           // contrast metrics: [n_map_wu] partials of the
-                              // interpolation units (NULL: not computed)
+    // ---- buffers (device memory; kernels address them as global memory,
+    //      whichever memory the descriptor itself is read from) ------------
+    const MC_GLOBAL void *in;
+    MC_GLOBAL void *out;
+    MC_GLOBAL uint32_t *part;           // [n_hist_wu][hG][nb]   partial histograms
+    MC_GLOBAL float *rpart;             // GHR: [n_range_wu][2]; AHR: [n_hist_wu][hG][2]
+    MC_GLOBAL uint32_t *hist;           // [nker][nb]
+    MC_GLOBAL unsigned long long *clipped;  // [nker][nb]
+    MC_GLOBAL float *lut;               // [nker][nb]
+    MC_GLOBAL float *range;             // GHR: [2]; AHR: [nker][2]
+    MC_GLOBAL float *scale;             // GHR: [1]; AHR: [nker]
+    MC_GLOBAL McMetPart *met;           // contrast metrics: [n_map_wu] partials of the
+                                        // interpolation units (NULL: not computed)
 };
 
 

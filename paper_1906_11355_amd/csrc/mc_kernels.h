@@ -103,13 +103,40 @@ __device__ __forceinline__ void load_chunk(const Tin *__restrict__ p, float (&f)
     }
 }
 
-// A read-only descriptor in device memory, seen through the constant
-// address space: loads from it are known not to be clobbered by the kernel's
-// stores, so its fields stay in registers (scalar loads) once read.
-__device__ __forceinline__ const McVol &mc_const_desc(const McVol *p)
+// Uniform copies of descriptor fields: scalar registers that the compiler
+// keeps for a whole loop.  The batched kernels read their descriptor from
+// device memory, and a field read inside a loop that stores to memory would
+// otherwise be reloaded (with a vector load) on every iteration.
+__device__ __forceinline__ int32_t mc_uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename T>
+__device__ __forceinline__ T *mc_uniform_ptr(T *p)
 {
-    typedef const __attribute__((address_space(4))) McVol CMcVol;
-    return *(const McVol *)(CMcVol *)p;
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ McAxis mc_uniform_axis(const McAxis &a)
+{
+    McAxis r;
+    r.s = mc_uniform(a.s);
+    r.b = mc_uniform(a.b);
+    r.p0 = mc_uniform(a.p0);
+    r.p1 = mc_uniform(a.p1);
+    r.n = mc_uniform(a.n);
+    r.cw = mc_uniform(a.cw);
+    return r;
+}
+__device__ __forceinline__ int64_t mc_uniform64(int64_t x)
+{
+    const uint64_t v = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ McBox mc_uniform_box(const McBox &b)
+{
+    return McBox{mc_uniform(b.lo), mc_uniform(b.hi), mc_uniform(b.olo), mc_uniform(b.ohi)};
 }
 
 __device__ __forceinline__ float load_elem(const void *in, int dt, int64_t i)
@@ -292,6 +319,19 @@ __device__ __forceinline__ void rowspace_finish(const McVol &d, RowSpace &rs)
     }
 }
 
+__device__ __forceinline__ void mc_uniform_rows(RowSpace &rs)
+{
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) {
+        rs.lo[i] = mc_uniform(rs.lo[i]);
+        rs.len[i] = mc_uniform(rs.len[i]);
+    }
+    rs.rows = mc_uniform64(rs.rows);
+    rs.in_lo = mc_uniform(rs.in_lo);
+    rs.in_len = mc_uniform(rs.in_len);
+    rs.in_stride = mc_uniform64(rs.in_stride);
+}
+
 // Decode o (flattened axes 0..D-3) into coordinates; unrolled with guards so
 // that every array index is a compile-time constant (no scratch memory).
 __device__ __forceinline__ void decode_outer(const McVol &d, const RowSpace &rs, int64_t o64,
@@ -344,6 +384,12 @@ __device__ __forceinline__ void hist_unit(const McVol &d, uint32_t wu, int64_t &
                                           McBox &ib)
 {
     ib = McBox{0, 1, 0, 0};
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) {
+        obox[i] = McBox{0, 1, 0, 0};
+        rs.lo[i] = 0;
+        rs.len[i] = 1;
+    }
     const int D = d.D;
     chunk = (int)(wu % (uint32_t)d.hCr);
     const uint32_t t1 = wu / (uint32_t)d.hCr;
@@ -378,6 +424,10 @@ __device__ __forceinline__ void build_hist_otab(const McVol &d, const RowSpace &
                                                 int cnt, HistOTab *tab)
 {
     const int D = d.D;
+    // the strides, read once (scalar registers) rather than per entry
+    int64_t st[MC_MAXD];
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) st[i] = i <= D - 3 ? mc_uniform64(d.stride[i]) : 0;
     for (int j = threadIdx.x; j < cnt; j += MC_T) {
         int32_t x[MC_MAXD];
         decode_outer(d, rs, o0 + j, x);
@@ -386,7 +436,7 @@ __device__ __forceinline__ void build_hist_otab(const McVol &d, const RowSpace &
 #pragma unroll
         for (int i = 0; i < MC_MAXD; ++i) {
             if (i <= D - 3) {
-                off += (int64_t)x[i] * d.stride[i];
+                off += (int64_t)x[i] * st[i];
                 w *= (uint32_t)mc_mult(obox[i], x[i]);
             }
         }
@@ -655,6 +705,12 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     RowSpace rs;
     McBox obox[MC_MAXD], ib;
     hist_unit(d, wu, col, seg, chunk, rs, obox, ib);
+    // the unit's geometry in scalar registers: kept, not recomputed from the
+    // descriptor inside the loops
+    mc_uniform_rows(rs);
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) obox[i] = mc_uniform_box(obox[i]);
+    ib = mc_uniform_box(ib);
     int kA, kB, xs, xe;
     hist_segment(d, seg, kA, kB, xs, xe);
     const int nslot = kB - kA;
@@ -1243,31 +1299,6 @@ __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int
 // m / (2b) as m times the single-precision reciprocal of 2b (exact for
 // power-of-two b, otherwise within one ulp; the same expression is used by
 // every kernel, so plain and batched results stay bit-identical).
-// Uniform copies of descriptor fields: scalar registers that the compiler
-// keeps for a whole loop.  The batched kernels read their descriptor from
-// device memory, and a field read inside a loop that stores to memory would
-// otherwise be reloaded (with a vector load) on every iteration.
-__device__ __forceinline__ int32_t mc_uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-template <typename T>
-__device__ __forceinline__ T *mc_uniform_ptr(T *p)
-{
-    const uint64_t v = (uint64_t)(uintptr_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ McAxis mc_uniform_axis(const McAxis &a)
-{
-    McAxis r;
-    r.s = mc_uniform(a.s);
-    r.b = mc_uniform(a.b);
-    r.p0 = mc_uniform(a.p0);
-    r.p1 = mc_uniform(a.p1);
-    r.n = mc_uniform(a.n);
-    r.cw = mc_uniform(a.cw);
-    return r;
-}
-
 __device__ __forceinline__ float cell_weight(const McAxis &a, int c, int x)
 {
     return (float)mc_cell_m(a, c, x) * (1.0f / (float)(2 * a.b));
@@ -1293,7 +1324,25 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     int chunk, grp;
     int32_t cidx[MC_MAXD];
     RowSpace rs;
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) {
+        cidx[i] = 0;
+        rs.lo[i] = 0;
+        rs.len[i] = 1;
+    }
     map_unit_decode(d, wu, chunk, grp, cidx, rs);
+    // the unit's geometry, and the outer axes and strides of its row table,
+    // in scalar registers (read once, not per table entry)
+    mc_uniform_rows(rs);
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) cidx[i] = mc_uniform(cidx[i]);
+    McAxis oax[MC_MAXD];
+    int64_t ost[MC_MAXD];
+#pragma unroll
+    for (int i = 0; i < MC_MAXD; ++i) {
+        oax[i] = i < D - 2 ? mc_uniform_axis(d.ax[i]) : McAxis{1, 1, 0, 0, 1, 0};
+        ost[i] = i < D - 2 ? mc_uniform64(d.stride[i]) : 0;
+    }
     const McAxis &al = d.ax[D - 1];
     int cA, cB, xs, xe, tmp;
     if (d.mP == 1) {
@@ -1456,8 +1505,8 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
             int n = 1;
 #pragma unroll
             for (int i = 0; i < D - 2; ++i) {
-                off += (int64_t)x[i] * d.stride[i];
-                const float w = cell_weight(d.ax[i], cidx[i], x[i]);
+                off += (int64_t)x[i] * ost[i];
+                const float w = cell_weight(oax[i], cidx[i], x[i]);
                 const float omw = 1.0f - w;
                 // tensor product, axis i becomes the next lower-order bit
 #pragma unroll

@@ -9,7 +9,8 @@ mclahe_status mc_fail(mclahe_status s, const char *fmt, ...);
 void mc_clear_error();
 
 typedef void (*KFn)(McVol);         // per-volume kernel: one volume by value
-typedef void (*KFnB)(McBatchSrc);   // batched twin: many volumes of one class
+typedef void (*KFnB)(McBatchSrc, const McVol *);   // batched twin: many volumes of one class
+                                                   // (the descriptors again, as a restrict parameter)
 
 struct KPair {
     KFn plain;

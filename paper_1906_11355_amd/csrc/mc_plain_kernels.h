@@ -7,20 +7,21 @@
 
 // Every kernel has a batched twin (suffix _b) that serves one pass of many
 // volumes of the same class: it finds its volume and unit in the launch's
-// index table and runs the very same unit function.  The volume index is
-// made a scalar value and the descriptor is read through the constant
-// address space (the table is written before the launch and never during
-// it): its fields then stay in scalar registers across the unit's stores, as
-// for a descriptor passed as a kernel argument, instead of being reloaded
-// with vector loads after every store that might alias the table.
-__device__ __forceinline__ const McVol &mc_resolve(const McBatchSrc &s, uint32_t &u)
+// index table and runs the very same unit function.  The volume descriptors
+// come as a kernel parameter of their own, declared restrict (the table is
+// written before the launch and only read during it): the compiler then
+// reads the descriptor with scalar loads and keeps its fields, as for a
+// descriptor passed by value, instead of reloading them with vector loads
+// after every store that might have written the table.
+__device__ __forceinline__ const McVol &mc_resolve(const McBatchSrc &s, const McVol *__restrict__ vols,
+                                                   uint32_t &u)
 {
     // the volume and unit are the work-group's own: scalar values
     const uint32_t r = blockIdx.x;
     const uint32_t j = __builtin_amdgcn_readfirstlane(mc_batch_volume(s.pre, s.n, r));
     u = __builtin_amdgcn_readfirstlane(r - s.pre[j]);
     const uint32_t vi = __builtin_amdgcn_readfirstlane(s.list[j]);
-    return mc::mc_const_desc(s.vols + vi);
+    return vols[vi];
 }
 
 template <typename Tin>
@@ -30,11 +31,11 @@ __global__ __launch_bounds__(MC_T) void k_range_ghr(McVol d)
     mc::range_ghr_unit<Tin>(d, blockIdx.x, smem);
 }
 template <typename Tin>
-__global__ __launch_bounds__(MC_T) void k_range_ghr_b(McBatchSrc s)
+__global__ __launch_bounds__(MC_T) void k_range_ghr_b(McBatchSrc s, const McVol *__restrict__ vols)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
-    const McVol &d = mc_resolve(s, u);
+    const McVol &d = mc_resolve(s, vols, u);
     mc::range_ghr_unit<Tin>(d, u, smem);
 }
 
@@ -45,11 +46,11 @@ __global__ __launch_bounds__(MC_T) void k_hist(McVol d)
     mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, blockIdx.x, smem);
 }
 template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
-__global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s)
+__global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s, const McVol *__restrict__ vols)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
-    const McVol &d = mc_resolve(s, u);
+    const McVol &d = mc_resolve(s, vols, u);
     mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, u, smem);
 }
 
@@ -60,11 +61,11 @@ __global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map(McVol d)
     mc::map_unit<Tin, D, AHR>(d, blockIdx.x, smem);
 }
 template <typename Tin, int D, bool AHR>
-__global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map_b(McBatchSrc s)
+__global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map_b(McBatchSrc s, const McVol *__restrict__ vols)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
-    const McVol &d = mc_resolve(s, u);
+    const McVol &d = mc_resolve(s, vols, u);
     mc::map_unit<Tin, D, AHR>(d, u, smem);
 }
 
@@ -75,11 +76,11 @@ __global__ __launch_bounds__(MC_T) void k_map_generic(McVol d)
     mc::map_unit_generic<Tin, AHR>(d, blockIdx.x, smem);
 }
 template <typename Tin, bool AHR>
-__global__ __launch_bounds__(MC_T) void k_map_generic_b(McBatchSrc s)
+__global__ __launch_bounds__(MC_T) void k_map_generic_b(McBatchSrc s, const McVol *__restrict__ vols)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
-    const McVol &d = mc_resolve(s, u);
+    const McVol &d = mc_resolve(s, vols, u);
     mc::map_unit_generic<Tin, AHR>(d, u, smem);
 }
 

@@ -525,15 +525,15 @@ static void batch_view(const mclahe_plan_s *p, mclahe_plan_s &q)
 static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, char *ws)
 {
     v = vec_aligned(p, in, out) ? p->v : p->v1;
-    v.in = in;
-    v.out = out;
-    v.part = (uint32_t *)(ws + p->o_part);
-    v.rpart = (float *)(ws + p->o_rpart);
-    v.hist = (uint32_t *)(ws + p->o_hist);
-    v.clipped = (unsigned long long *)(ws + p->o_clipped);
-    v.lut = (float *)(ws + p->o_lut);
-    v.range = (float *)(ws + p->o_range);
-    v.scale = (float *)(ws + p->o_scale);
+    v.in = mc_gp(in);
+    v.out = mc_gp(out);
+    v.part = mc_gp((uint32_t *)(ws + p->o_part));
+    v.rpart = mc_gp((float *)(ws + p->o_rpart));
+    v.hist = mc_gp((uint32_t *)(ws + p->o_hist));
+    v.clipped = mc_gp((unsigned long long *)(ws + p->o_clipped));
+    v.lut = mc_gp((float *)(ws + p->o_lut));
+    v.range = mc_gp((float *)(ws + p->o_range));
+    v.scale = mc_gp((float *)(ws + p->o_scale));
 }
 
 // Kernel selection lives in the per-dtype translation units (k_plain_*.hip).
@@ -545,11 +545,11 @@ __global__ __launch_bounds__(MC_T) void k_clip(McVol d)
     extern __shared__ __align__(16) char smem[];
     mc::clip_unit(d, blockIdx.x, smem);
 }
-__global__ __launch_bounds__(MC_T) void k_clip_b(McBatchSrc s)
+__global__ __launch_bounds__(MC_T) void k_clip_b(McBatchSrc s, const McVol *__restrict__ vols)
 {
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
-    const McVol &d = mc_resolve(s, u);
+    const McVol &d = mc_resolve(s, vols, u);
     mc::clip_unit(d, u, smem);
 }
 
@@ -809,10 +809,10 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
         const int X = nin & 1;
         if ((s = upload(X, 0, g.rr0[b], g.rr1[b]))) return s;
         McVol v = p->v;
-        v.in = inbuf[X];
+        v.in = mc_gp(inbuf[X]);
         v.nvox = (g.rr1[b] - g.rr0[b]) * g.row_elems;
         v.n_range_wu = g.rparts[b];
-        v.rpart = (float *)(ws + g.o_rpart) + 2 * (size_t)rp;
+        v.rpart = mc_gp((float *)(ws + g.o_rpart) + 2 * (size_t)rp);
 
         const KPair k = phase_kernels(p, v, 0, lds);
         if ((s = launch(k.plain, v.n_range_wu, k.threads, lds, st, v))) return s;
@@ -859,19 +859,19 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
         v.n_hist_wu = (uint32_t)((int64_t)nl * g.cols_per_layer * v.hS * v.hCr);
         v.n_clip_wu = (uint32_t)((int64_t)nl * g.layer_kernels);
         v.n_range_wu = g.range_parts;
-        v.in = sin;
+        v.in = mc_gp(sin);
         v.out = nullptr;
-        v.part = (uint32_t *)(ws + g.o_part);
-        v.rpart = (float *)(ws + g.o_rpart);
-        v.hist = (uint32_t *)(ws + g.o_hist);
-        v.clipped = (unsigned long long *)(ws + g.o_clipped);
-        v.lut = lutb + layer_lut;                     // slab layers after the halo
+        v.part = mc_gp((uint32_t *)(ws + g.o_part));
+        v.rpart = mc_gp((float *)(ws + g.o_rpart));
+        v.hist = mc_gp((uint32_t *)(ws + g.o_hist));
+        v.clipped = mc_gp((unsigned long long *)(ws + g.o_clipped));
+        v.lut = mc_gp(lutb + layer_lut);                     // slab layers after the halo
         if (ahr) {
-            v.range = mrange + (size_t)g.layer_kernels * 2;
-            v.scale = mscale + g.layer_kernels;
+            v.range = mc_gp(mrange + (size_t)g.layer_kernels * 2);
+            v.scale = mc_gp(mscale + g.layer_kernels);
         } else {
-            v.range = (float *)(ws + g.o_range);
-            v.scale = (float *)(ws + g.o_scale);
+            v.range = mc_gp((float *)(ws + g.o_range));
+            v.scale = mc_gp((float *)(ws + g.o_scale));
         }
         for (int ph = 0; ph < 3; ++ph) {
             const KPair k = phase_kernels(p, v, ph, lds);
@@ -884,13 +884,13 @@ static mclahe_status run_chunked(const mclahe_plan_s *p, const ChunkGeom &g, con
             McVol m = v;
             m.wc0 = cA;
             m.n_map_wu = (uint32_t)((int64_t)(cB - cA) * g.mcols_per_layer * v.mS * v.mU);
-            m.in = sin;
-            m.out = sout;
+            m.in = mc_gp(sin);
+            m.out = mc_gp(sout);
             // LUT layer 0 of the buffer is global kernel layer kA - 1
-            m.lut = lutb - (int64_t)(kA - 1) * (int64_t)layer_lut;
+            m.lut = mc_gp(lutb - (int64_t)(kA - 1) * (int64_t)layer_lut);
             if (ahr) {
-                m.range = mrange - (int64_t)(kA - 1) * g.layer_kernels * 2;
-                m.scale = mscale - (int64_t)(kA - 1) * g.layer_kernels;
+                m.range = mc_gp(mrange - (int64_t)(kA - 1) * g.layer_kernels * 2);
+                m.scale = mc_gp(mscale - (int64_t)(kA - 1) * g.layer_kernels);
             }
             if (out_used[Y]) HIPCHK(hipStreamWaitEvent(st, cs->out_free[Y], 0));
             const KPair k = phase_kernels(p, m, 3, lds);
@@ -1176,7 +1176,8 @@ static mclahe_status build_graph(GraphEntry *g, const BatchLayout &L, const std:
         src.pre = idx_dev + recs[j].pre;
         src.n = recs[j].n;
         src.pad_ = 0;
-        void *args[] = {&src};
+        const McVol *vols_arg = vols_dev;
+        void *args[] = {&src, &vols_arg};
         hipKernelNodeParams kp = {};
         kp.func = (void *)bl.fn;
         kp.gridDim = dim3(recs[j].units);
@@ -1571,7 +1572,7 @@ mclahe_status mclahe_run_metrics(mclahe_plan_t p, const void *d_in, void *d_out,
     if ((s = check_run_args(p, d_in, d_out, d_ws, wsb, need))) return s;
     McVol v;
     bind(p, v, d_in, d_out, (char *)d_ws);
-    v.met = (McMetPart *)((char *)d_ws + met_parts_off(p));
+    v.met = mc_gp((McMetPart *)((char *)d_ws + met_parts_off(p)));
     hipStream_t st = (hipStream_t)stream;
     for (int ph = 0; ph < 3; ++ph) {
         size_t lds = 0;
@@ -1837,7 +1838,7 @@ static mclahe_status batched_direct(const BatchLayout &L, const std::vector<char
             HIPCHK(hipFuncSetAttribute((const void *)bl.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)bl.lds));
         McBatchSrc src{vols_dev, idx_dev + recs[j].list, idx_dev + recs[j].pre, recs[j].n, 0};
-        hipLaunchKernelGGL(bl.fn, dim3(recs[j].units), dim3(bl.threads), bl.lds, st, src);
+        hipLaunchKernelGGL(bl.fn, dim3(recs[j].units), dim3(bl.threads), bl.lds, st, src, src.vols);
         HIPCHK(hipGetLastError());
     }
     return MCLAHE_SUCCESS;
@@ -1992,7 +1993,8 @@ static mclahe_status persistent_launch(const BatchLayout &L, const std::vector<c
             if ((s = stage_table(img, table, st))) return s;
             hipLaunchKernelGGL((void (*)(uint32_t *, uint32_t))mc_persist_reset_fn(), dim3(rgrid), dim3(MC_T), 0, st,
                                q, nq);
-            hipLaunchKernelGGL((void (*)(McPersistSrc))mc_persist_fn(), dim3(grid), dim3(MC_T), lds, st, src);
+            hipLaunchKernelGGL((void (*)(McPersistSrc, const McVol *))mc_persist_fn(), dim3(grid), dim3(MC_T), lds, st,
+                               src, src.vols);
             HIPCHK(hipGetLastError());
             return MCLAHE_SUCCESS;
         }
@@ -2030,7 +2032,8 @@ static mclahe_status persistent_launch(const BatchLayout &L, const std::vector<c
             hipGraphNode_t nr, np;
             HIPCHK(hipGraphAddKernelNode(&nr, g->graph, nullptr, 0, &kr));
             hipKernelNodeParams kp = {};
-            void *pargs[] = {&src};
+            const McVol *vols_arg = src.vols;
+            void *pargs[] = {&src, &vols_arg};
             kp.func = (void *)mc_persist_fn();
             kp.gridDim = dim3(grid);
             kp.blockDim = dim3(MC_T);
