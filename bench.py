@@ -720,6 +720,25 @@ def mix_alg_bytes(items, out_size=4):
     return sum(int(it.x.size) * (3 * it.x.dtype.itemsize + out_size) for it in items)
 
 
+def steady_ms(torch, f, k=20, warm=20, reps=3):
+    """Steady-state ms per call of f: the median of `reps` timings of k calls
+    back to back, after `warm` calls.  The first call of a batch launches
+    directly, the second captures its graph, and the first replays of a new
+    graph (upload) and the clocks settle over the warm-up; one timing right
+    after it still read up to 20 % slow on the mixed batch."""
+    for _ in range(warm):
+        f()
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            f()
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t) / k * 1e3)
+    return sorted(out)[len(out) // 2], out
+
+
 def bench_batched_graph(torch, _lib, items, dev, steps, warm, persistent=False):
     """The mixed batch through mclahe_run_batched only (graph replays), or
     through the single persistent launch."""
@@ -732,18 +751,11 @@ def bench_batched_graph(torch, _lib, items, dev, steps, warm, persistent=False):
     st = torch.cuda.current_stream(dev).cuda_stream
     ins, ops = [x.data_ptr() for x in xs], [o.data_ptr() for o in outs]
     run = _lib.run_batched_persistent_ptr if persistent else _lib.run_batched_ptr
-    for _ in range(warm):
-        run(plans, ins, ops, ws.data_ptr(), ws.numel(), st)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
-        run(plans, ins, ops, ws.data_ptr(), ws.numel(), st)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t) / max(1, steps) * 1e3
+    ms, reps = steady_ms(torch, lambda: run(plans, ins, ops, ws.data_ptr(), ws.numel(), st), steps, warm)
     alg = mix_alg_bytes(items)
     return {"leg": "persistent" if persistent else "batched_graph", "volumes": len(items),
             "classes": sorted({it.kind for it in items}), "steps": steps, "warmup": warm,
-            "batched_ms": round(ms, 4), "alg_bytes": alg,
+            "batched_ms": round(ms, 4), "repeats_ms": [round(r, 4) for r in reps], "alg_bytes": alg,
             "frac_of_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
@@ -778,17 +790,7 @@ def bench_batched(torch, np, _lib, items, dev):
                                    tbl.numel(), st)
 
     def timeit(f, k=20, warm=20):
-        # the first call launches directly, the second captures the batch's
-        # graph, the next ones replay it; the first replays of a new graph
-        # and the clocks settle within about 20 calls: time the steady state
-        for _ in range(warm):
-            f()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(k):
-            f()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / k * 1e3
+        return steady_ms(torch, f, k, warm)[0]
 
     outs_q = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in xs]
     wsq = torch.empty(_lib.batched_workspace_size(plans), dtype=torch.uint8, device=dev)

@@ -166,6 +166,7 @@ __global__ __launch_bounds__(MC_T, 2) void k_persist(McPersistSrc s, const McVol
             // the range pass reads only the input
             if (ph > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const McVol &v = vols[vi];
+            mc::warm_desc(v);
             const uint32_t u = uw & 0x7fffffffu;
             if (v.in_dt == MC_U8) persist_unit<uint8_t>(v, ph, u, smem);
             else if (v.in_dt == MC_U16) persist_unit<uint16_t>(v, ph, u, smem);

@@ -33,6 +33,37 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Touch every 64-byte line of a volume descriptor with loads issued
+// together, before any field is used.  Fields are read where they are
+// needed, many behind branches on others, and a launch's descriptor is in no
+// cache yet (fresh kernel arguments, or a table just uploaded): without this
+// the first read of each line waited for memory in turn, a chain of misses
+// that dominated the duration of small launches.
+__device__ __forceinline__ void warm_desc(const McVol &d)
+{
+    const char *p = reinterpret_cast<const char *>(&d);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < (int)sizeof(McVol); i += 64) {
+        uint32_t w;
+        __builtin_memcpy(&w, p + i, sizeof w);
+        acc ^= w;
+    }
+    asm volatile("; descriptor lines resident %0" ::"s"(acc));
+}
+
+// a / b for a >= 0 and b > 0 (b < 2^31).  The row counts and offsets a unit
+// divides (one kernel column or cell box) nearly always fit 32 bits: a
+// 32-bit division is a short instruction sequence, a 64-bit one a long one
+// that dominated the set-up of small units, so the wide one runs only when
+// a needs it.
+__device__ __forceinline__ int64_t mc_div(int64_t a, int64_t b)
+{
+    if ((uint64_t)a <= 0xffffffffull && (uint64_t)b <= 0xffffffffull)
+        return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
+
 // Bin of v (single precision, no contraction; identical to the reading used
 // by the oracle; scale = +inf for a degenerate range gives 0 / n-1 as well).
 __device__ __forceinline__ int bin_of(float v, float lo, float scale, float nbf, int nbm1)
@@ -372,8 +403,8 @@ __device__ __forceinline__ void hist_segment(const McVol &d, int j, int &kA, int
         const int pp = j - kA * d.hP;
         const McBox b = mc_kernel_box(a, kA);
         const int len = b.hi - b.lo;
-        xs = b.lo + (int)((int64_t)len * pp / d.hP);
-        xe = b.lo + (int)((int64_t)len * (pp + 1) / d.hP);
+        xs = b.lo + (int)mc_div((int64_t)len * pp, d.hP);
+        xe = b.lo + (int)mc_div((int64_t)len * (pp + 1), d.hP);
     }
 }
 
@@ -399,7 +430,7 @@ __device__ __forceinline__ void hist_unit(const McVol &d, uint32_t wu, int64_t &
 #pragma unroll
     for (int i = MC_MAXD - 2; i >= 0; --i) {
         if (i <= D - 2) {
-            const int64_t q = c / d.ax[i].n;
+            const int64_t q = mc_div(c, d.ax[i].n);
             const int k = (int)(c - q * d.ax[i].n) + (i == 0 ? d.wk0 : 0);
             c = q;
             obox[i] = mc_kernel_box(d.ax[i], k);
@@ -720,9 +751,9 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     const int SS = mc_hist_slot_stride(nb, R);
 
     // rows of this chunk
-    const int64_t r0 = rs.rows * chunk / d.hCr, r1 = rs.rows * (chunk + 1) / d.hCr;
-    const int64_t o0 = r0 / rs.in_len;
-    const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
+    const int64_t r0 = mc_div(rs.rows * chunk, d.hCr), r1 = mc_div(rs.rows * (chunk + 1), d.hCr);
+    const int64_t o0 = mc_div(r0, rs.in_len);
+    const int ocnt = r1 > r0 ? (int)(mc_div(r1 - 1, rs.in_len) - o0 + 1) : 0;
     build_hist_otab(d, rs, obox, o0, ocnt, L.otab);
 
     // global range (GHR) or this unit's kernels' ranges (AHR)
@@ -834,9 +865,9 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
     const Tin *in = (const Tin *)d.in;
     if (tact) {
         const int64_t rstart = r0 + trow;
-        int64_t o = rstart / rs.in_len;
+        int64_t o = mc_div(rstart, rs.in_len);
         int r = (int)(rstart - o * rs.in_len);
-        const int64_t so = rpi / rs.in_len;
+        const int64_t so = mc_div(rpi, rs.in_len);
         const int sr = (int)(rpi - so * rs.in_len);
         const int64_t xoff = xl;
         // U rows per step.  Software pipelined: the loads of the next U rows
@@ -1086,7 +1117,7 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
     unsigned long long *s64 = (unsigned long long *)smem;
     const int nb = d.nb;
     const int nl = d.ax[d.D - 1].n;
-    const int64_t col = (int64_t)k / nl;
+    const int64_t col = mc_div((int64_t)k, nl);
     const int kl = (int)(k - col * nl);
     int sg0, nsg, sl;
     if (d.hP == 1) { sg0 = kl / d.hG; nsg = 1; sl = kl - sg0 * d.hG; }
@@ -1283,7 +1314,7 @@ __device__ __forceinline__ void map_unit_decode(const McVol &d, uint32_t wu, int
     for (int i = MC_MAXD - 2; i >= 0; --i) {
         if (i <= D - 2) {
             const int nc = d.ax[i].n - 1;
-            const int64_t q = c / nc;
+            const int64_t q = mc_div(c, nc);
             cidx[i] = (int)(c - q * nc) + (i == 0 ? d.wc0 : 0);
             c = q;
             int lo, hi;
@@ -1356,8 +1387,8 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int pp = grp - cA * d.mP;
         int lo, hi;
         mc_cell_range(al, cA, lo, hi);
-        xs = lo + (int)((int64_t)(hi - lo) * pp / d.mP);
-        xe = lo + (int)((int64_t)(hi - lo) * (pp + 1) / d.mP);
+        xs = lo + (int)mc_div((int64_t)(hi - lo) * pp, d.mP);
+        xe = lo + (int)mc_div((int64_t)(hi - lo) * (pp + 1), d.mP);
     }
     const int ncl = cB - cA;
 
@@ -1478,7 +1509,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const Tin *in = (const Tin *)d.in;
     const float nbf = (float)nb;
     const int nbm1 = nb - 1;
-    const int64_t so = rpi / rs.in_len;
+    const int64_t so = mc_div(rpi, rs.in_len);
     const int sr = (int)(rpi - so * rs.in_len);
     // descriptor fields of the row loop, held in scalar registers
     const McAxis aw = mc_uniform_axis(d.ax[D >= 2 ? D - 2 : 0]);
@@ -1492,9 +1523,9 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     // registers without spilling)
     const int chA = chunk * d.mK, chB = AHR ? chA + 1 : mc_min(chA + d.mK, d.mCr);
     for (int ch = chA; ch < chB; ++ch) {
-        const int64_t r0 = rs.rows * ch / d.mCr, r1 = rs.rows * (ch + 1) / d.mCr;
-        const int64_t o0 = r0 / rs.in_len;
-        const int ocnt = r1 > r0 ? (int)((r1 - 1) / rs.in_len - o0 + 1) : 0;
+        const int64_t r0 = mc_div(rs.rows * ch, d.mCr), r1 = mc_div(rs.rows * (ch + 1), d.mCr);
+        const int64_t o0 = mc_div(r0, rs.in_len);
+        const int ocnt = r1 > r0 ? (int)(mc_div(r1 - 1, rs.in_len) - o0 + 1) : 0;
         if (ch > chA) __syncthreads();   // every reader of the previous table is done
         for (int j = threadIdx.x; j < ocnt; j += NT) {
             int32_t x[MC_MAXD];
@@ -1525,7 +1556,7 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
         __syncthreads();
         if (!tact) continue;
         const int64_t rstart = r0 + trow;
-        int64_t o = rstart / rs.in_len;
+        int64_t o = mc_div(rstart, rs.in_len);
         int r = (int)(rstart - o * rs.in_len);
         // rows whose loads are in flight together (with NT threads and two
         // units per CU this keeps ~64 KiB of loads in flight per CU)
@@ -1695,7 +1726,7 @@ __device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
         glo = d.range[0];
         gsc = d.scale[0];
     }
-    const int64_t r0 = rs.rows * chunk / d.mCr, r1 = rs.rows * (chunk + 1) / d.mCr;
+    const int64_t r0 = mc_div(rs.rows * chunk, d.mCr), r1 = mc_div(rs.rows * (chunk + 1), d.mCr);
     const int xl = xe - xs;
     const int64_t nel = (r1 - r0) * xl;
     const float nbf = (float)nb;
@@ -1703,7 +1734,7 @@ __device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
     MetAcc macc;
     if constexpr (MET) macc.init();
     for (int64_t e = threadIdx.x; e < nel; e += MC_T) {
-        const int64_t row = r0 + e / xl;
+        const int64_t row = r0 + mc_div(e, xl);
         const int x = xs + (int)(e - (row - r0) * xl);
         // decode the row into outer coordinates
         int32_t xc[MC_MAXD];
@@ -1712,7 +1743,7 @@ __device__ void map_unit_generic(const McVol &d, uint32_t wu, char *smem)
 #pragma unroll
         for (int i = MC_MAXD - 2; i >= 0; --i) {
             if (i <= D - 2) {
-                const int64_t q = rr / rs.len[i];
+                const int64_t q = mc_div(rr, rs.len[i]);
                 xc[i] = rs.lo[i] + (int)(rr - q * rs.len[i]);
                 rr = q;
                 off += (int64_t)xc[i] * d.stride[i];

@@ -21,6 +21,7 @@ __device__ __forceinline__ const McVol &mc_resolve(const McBatchSrc &s, const Mc
     const uint32_t j = __builtin_amdgcn_readfirstlane(mc_batch_volume(s.pre, s.n, r));
     u = __builtin_amdgcn_readfirstlane(r - s.pre[j]);
     const uint32_t vi = __builtin_amdgcn_readfirstlane(s.list[j]);
+    mc::warm_desc(vols[vi]);
     return vols[vi];
 }
 
@@ -28,6 +29,7 @@ template <typename Tin>
 __global__ __launch_bounds__(MC_T) void k_range_ghr(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::range_ghr_unit<Tin>(d, blockIdx.x, smem);
 }
 template <typename Tin>
@@ -43,6 +45,7 @@ template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
 __global__ __launch_bounds__(MC_T) void k_hist(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, blockIdx.x, smem);
 }
 template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
@@ -58,6 +61,7 @@ template <typename Tin, int D, bool AHR>
 __global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::map_unit<Tin, D, AHR>(d, blockIdx.x, smem);
 }
 template <typename Tin, int D, bool AHR>
@@ -73,6 +77,7 @@ template <typename Tin, bool AHR>
 __global__ __launch_bounds__(MC_T) void k_map_generic(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::map_unit_generic<Tin, AHR>(d, blockIdx.x, smem);
 }
 template <typename Tin, bool AHR>
@@ -91,12 +96,14 @@ template <typename Tin, int D, bool AHR>
 __global__ __launch_bounds__(mc_map_threads(AHR), 4) void k_map_m(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::map_unit<Tin, D, AHR, true>(d, blockIdx.x, smem);
 }
 template <typename Tin, bool AHR>
 __global__ __launch_bounds__(MC_T) void k_map_generic_m(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::map_unit_generic<Tin, AHR, true>(d, blockIdx.x, smem);
 }
 

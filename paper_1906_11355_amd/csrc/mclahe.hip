@@ -543,6 +543,7 @@ static void bind(const mclahe_plan_s *p, McVol &v, const void *in, void *out, ch
 __global__ __launch_bounds__(MC_T) void k_clip(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
+    mc::warm_desc(d);
     mc::clip_unit(d, blockIdx.x, smem);
 }
 __global__ __launch_bounds__(MC_T) void k_clip_b(McBatchSrc s, const McVol *__restrict__ vols)
