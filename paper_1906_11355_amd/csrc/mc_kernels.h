@@ -545,6 +545,31 @@ __device__ void range_ghr_unit(const McVol &d, uint32_t u, char *smem)
     else range_ghr_unit_v<Tin, 1>(d, u, (float *)smem);
 }
 
+// Work-group minimum and maximum (every thread gets both): butterfly
+// shuffles inside each wave, then the MC_T / 64 wave results through LDS
+// (ri: 2 MC_T / 64 ints).  Atomics of every lane to one LDS word were
+// compiled into a loop over the active lanes, some 900 scalar instructions
+// per wave, which dominated the set-up of a unit.
+__device__ __forceinline__ void block_minmax_i32(int &mn, int &mx, int *ri)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = mc_min(mn, __shfl_xor(mn, o));
+        mx = mc_max(mx, __shfl_xor(mx, o));
+    }
+    if (lane_id() == 0) {
+        ri[2 * (threadIdx.x >> 6)] = mn;
+        ri[2 * (threadIdx.x >> 6) + 1] = mx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < MC_T / 64; ++w) {
+        mn = mc_min(mn, ri[2 * w]);
+        mx = mc_max(mx, ri[2 * w + 1]);
+    }
+    __syncthreads();   // ri may be written again
+}
+
 // Reduce the GHR partials (or take the user range); every unit that calls
 // this gets the same lo, hi and scale.
 __device__ __forceinline__ void ghr_range(const McVol &d, float *red, float &lo, float &hi,
@@ -571,18 +596,10 @@ __device__ __forceinline__ void ghr_range(const McVol &d, float *red, float &lo,
                 mx = fmaxf(mx, pv[q].y);
             }
         }
-        int *ri = (int *)red;
-        if (threadIdx.x == 0) {
-            ri[0] = 0x7fffffff;
-            ri[1] = (int)0x80000000;
-        }
-        __syncthreads();
-        atomicMin(&ri[0], f2o(mn));
-        atomicMax(&ri[1], f2o(mx));
-        __syncthreads();
-        lo = o2f(ri[0]);
-        hi = o2f(ri[1]);
-        __syncthreads();
+        int imn = f2o(mn), imx = f2o(mx);
+        block_minmax_i32(imn, imx, (int *)red);
+        lo = o2f(imn);
+        hi = o2f(imx);
     }
     scale = range_scale(d.nb, lo, hi);
 }
@@ -1028,20 +1045,10 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         if constexpr (VAL && !AHR) {
             // the unit's (min, max) value, for the global range of the clip
             // pass (+inf/-inf when the unit counted nothing)
-            int *ri = (int *)L.red;
+            block_minmax_i32(vmin, vmax, (int *)L.red);
             if (threadIdx.x == 0) {
-                ri[0] = 256;
-                ri[1] = -1;
-            }
-            __syncthreads();
-            if (vmax >= 0) {
-                atomicMin(&ri[0], vmin);
-                atomicMax(&ri[1], vmax);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                d.rpart[2 * (int64_t)wu] = ri[1] >= 0 ? (float)ri[0] : INFINITY;
-                d.rpart[2 * (int64_t)wu + 1] = ri[1] >= 0 ? (float)ri[1] : -INFINITY;
+                d.rpart[2 * (int64_t)wu] = vmax >= 0 ? (float)vmin : INFINITY;
+                d.rpart[2 * (int64_t)wu + 1] = vmax >= 0 ? (float)vmax : -INFINITY;
             }
         }
     }
@@ -1166,8 +1173,7 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
             lo = d.user_lo;
             hi = d.user_hi;
         } else {
-            // order-preserving integers, reduced by wave shuffles, then
-            // across the MC_T / 64 waves
+            // order-preserving integers
             int mn = 0x7fffffff, mx = (int)0x80000000;
             if (d.mode == MC_AHR) {
                 if (cnt) mn = mx = f2o((float)v);
@@ -1191,22 +1197,7 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
                     }
                 }
             }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                mn = mc_min(mn, __shfl_xor(mn, o));
-                mx = mc_max(mx, __shfl_xor(mx, o));
-            }
-            int *ri = (int *)smem;
-            if (lane_id() == 0) {
-                ri[2 * (threadIdx.x >> 6)] = mn;
-                ri[2 * (threadIdx.x >> 6) + 1] = mx;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int w = 0; w < MC_T / 64; ++w) {
-                mn = mc_min(mn, ri[2 * w]);
-                mx = mc_max(mx, ri[2 * w + 1]);
-            }
+            block_minmax_i32(mn, mx, (int *)smem);
             lo = o2f(mn);
             hi = o2f(mx);
         }
