@@ -31,6 +31,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, published peak
+# vector issue: 256 CUs x 2.4 GHz x 64 lanes (the 157.3 TFLOP/s fp32 peak without FMA and packing)
+VALU_PEAK_TLANE = 39.32
 METRIC = "Gvoxel/s + %HBM roofline, 4D fp32 MCLAHE; batched vs plain; serving p50/p99"
 SHAPE = (256, 256, 128, 32)
 KSIZE = (32, 32, 16, 8)
@@ -710,6 +712,16 @@ def bench_configs(torch, np, _lib, synth, x4, dev):
                      "us_per_step_back_to_back": round(ms_b2b * 1e3, 1),
                      "Gvoxel_s": round(V / ms / 1e6, 2), "pass_ms": passes,
                      "path_frac_of_hbm": round(V * (3 * S + 4) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if mode == "kernel":
+            # per-kernel ranges: the interpolation bins every voxel once per
+            # corner kernel; its floor is 6 vector instructions per corner
+            # (subtract, multiply, convert, min, LUT address, FMA), issued at
+            # 64 lanes per CU per cycle (no packed FP32)
+            per_vox = 6 * (1 << x.ndim)
+            ach = V * per_vox / (passes["map"] * 1e-3) / 1e12
+            out[name]["map_roofline"] = {"bound": "alu", "achieved": round(ach, 2), "peak": VALU_PEAK_TLANE,
+                                         "unit": "T lane instructions/s", "frac": round(ach / VALU_PEAK_TLANE, 4),
+                                         "alg_instructions_per_voxel": per_vox}
     return out
 
 
