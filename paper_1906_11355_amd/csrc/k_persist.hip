@@ -45,7 +45,7 @@ template <typename Tin, bool AHR, bool RO, bool VAL = false>
 __device__ __noinline__ void pu_hist(const McVol &v, uint32_t u, char *smem)
 {
     // wavefront aggregation changes no count: the plain update serves all
-    mc::hist_unit_dispatch<Tin, AHR, RO, 0, VAL>(v, u, smem);
+    mc::hist_unit_dispatch<Tin, AHR, RO, 0, VAL, 2>(v, u, smem);
 }
 template <typename Tin>
 __device__ __noinline__ void pu_range(const McVol &v, uint32_t u, char *smem)

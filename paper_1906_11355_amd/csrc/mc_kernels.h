@@ -742,7 +742,7 @@ __device__ __forceinline__ void hist_add(uint32_t *h, int key, uint32_t val, int
 // bins; no range is needed here (the clip pass takes it and re-bins), and
 // under a global range each unit also writes the smallest and largest value
 // it counted.
-template <typename Tin, int V, bool AHR, bool RANGE_ONLY, int PEEL, bool VAL = false>
+template <typename Tin, int V, bool AHR, bool RANGE_ONLY, int PEEL, bool VAL = false, int UW = 4>
 __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
 {
     static_assert(!VAL || (sizeof(Tin) == 1 && !RANGE_ONLY), "value slots: uint8 counting only");
@@ -889,8 +889,12 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         const int64_t xoff = xl;
         // U rows per step.  Software pipelined: the loads of the next U rows
         // are issued before the current U rows are binned, so every wave
-        // keeps up to 2U wide loads in flight while it works.
-        constexpr int U = V >= 8 ? 2 : 4;
+        // keeps up to 2U wide loads in flight while it works.  UW: rows per
+        // step of 16-byte chunks (4 for a volume alone; batched launches take
+        // 2, which needs 77 instead of 111 VGPRs, six waves per SIMD instead
+        // of four: faster on the many small units of a batch, slower on the
+        // large ones of a volume alone)
+        constexpr int U = V >= 8 ? 2 : UW;
         auto prep_load = [&](int64_t rw, uint32_t (&wr)[U], bool (&okk)[U], float (&fl)[U][V]) {
             int64_t offs[U];
 #pragma unroll
@@ -1056,12 +1060,12 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
 
 // VAL: value slots (uint8 input with d.vhist set), a kernel of its own so
 // that each variant gets the registers it needs
-template <typename Tin, bool AHR, bool RANGE_ONLY, int PEEL, bool VAL = false>
+template <typename Tin, bool AHR, bool RANGE_ONLY, int PEEL, bool VAL = false, int UW = 4>
 __device__ void hist_unit_dispatch(const McVol &d, uint32_t wu, char *smem)
 {
     constexpr int VM = mc_vec_elems((int)sizeof(Tin));
-    if (d.vec == VM) hist_unit_v<Tin, VM, AHR, RANGE_ONLY, PEEL, VAL>(d, wu, smem);
-    else hist_unit_v<Tin, 1, AHR, RANGE_ONLY, PEEL, VAL>(d, wu, smem);
+    if (d.vec == VM) hist_unit_v<Tin, VM, AHR, RANGE_ONLY, PEEL, VAL, UW>(d, wu, smem);
+    else hist_unit_v<Tin, 1, AHR, RANGE_ONLY, PEEL, VAL, UW>(d, wu, smem);
 }
 
 // ----------------------------------------------------- clip + CDF + LUT --

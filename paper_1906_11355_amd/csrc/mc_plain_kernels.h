@@ -46,7 +46,8 @@ __global__ __launch_bounds__(MC_T) void k_hist(McVol d)
 {
     extern __shared__ __align__(16) char smem[];
     mc::warm_desc(d);
-    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, blockIdx.x, smem);
+    // wave aggregation needs the registers of two rows per step (four spill)
+    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL, (PEEL > 0 ? 2 : 4)>(d, blockIdx.x, smem);
 }
 template <typename Tin, bool AHR, bool RO, int PEEL, bool VAL = false>
 __global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s, const McVol *__restrict__ vols)
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(MC_T) void k_hist_b(McBatchSrc s, const McVol *__re
     extern __shared__ __align__(16) char smem[];
     uint32_t u;
     const McVol &d = mc_resolve(s, vols, u);
-    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL>(d, u, smem);
+    mc::hist_unit_dispatch<Tin, AHR, RO, PEEL, VAL, 2>(d, u, smem);
 }
 
 template <typename Tin, int D, bool AHR>
