@@ -1244,24 +1244,41 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
         smin += h < C ? h : C;
         exc += h > C ? h - C : 0ull;
     }
-    const unsigned long long E = block_sum_u64(exc, s64);
+    // One block pass with one barrier: the sum of min(h, C) over the bins
+    // of the threads before this one (wave scans, then the wave totals
+    // through LDS), the block totals of min(h, C) and of the excess E, and
+    // bin 0's min(h, C).  With H_j = n min(h_j, C) + E, the prefix of H
+    // before bin j0, H_0 and the total of H follow in exact integers (the
+    // bins are dealt to the threads in order, j0 of them before this one).
+    constexpr int NW = MC_T / 64;
+    const int w = (int)(threadIdx.x >> 6);
+    const unsigned long long sinc = wave_incl_scan_u64(smin);
+    const unsigned long long esum = wave_sum_u64(exc);
+    if (lane_id() == 63) s64[w] = sinc;
+    if (lane_id() == 0) s64[NW + w] = esum;
+    if (threadIdx.x == 0) {
+        const uint32_t h0 = hk[0];   // bin 0 is thread 0's own
+        s64[2 * NW] = h0 < C ? h0 : C;
+    }
+    __syncthreads();
+    unsigned long long spre = sinc - smin, stot = 0, E = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        stot += s64[q];
+        spre += q < w ? s64[q] : 0ull;
+        E += s64[NW + q];
+    }
+    const unsigned long long m0 = s64[2 * NW];
     const unsigned long long nbu = (unsigned long long)nb;
     if (d.redist != MC_REDIST_EQUAL) {
+        __syncthreads();   // every thread has read the exchange before it is reused
         clip_variant(d, k, hk, j0, j1, C, E, s64);
         return;
     }
-    const unsigned long long tsum = nbu * smin + (unsigned long long)(j1 - j0) * E;
-    const unsigned long long pre = block_exscan_u64(tsum, s64);
     // c0 = H_0, total = sum H (= n*K); both block-uniform
-    if (threadIdx.x == MC_T - 1) s64[0] = pre + tsum;
-    if (threadIdx.x == 0) {
-        const uint32_t h0 = hk[0];
-        s64[1] = nbu * (h0 < C ? h0 : C) + E;
-    }
-    __syncthreads();
-    const unsigned long long total = s64[0], c0 = s64[1];
+    const unsigned long long total = nbu * stot + nbu * E, c0 = nbu * m0 + E;
     const unsigned long long den = total - c0;
-    unsigned long long acc = pre;
+    unsigned long long acc = nbu * spre + (unsigned long long)j0 * E;
     unsigned long long *Hk = d.clipped + (int64_t)k * nb;
     float *lk = d.lut + (int64_t)k * nb;
     for (int j = j0; j < j1; ++j) {
