@@ -549,8 +549,9 @@ __device__ void range_ghr_unit(const McVol &d, uint32_t u, char *smem)
 // shuffles inside each wave, then the MC_T / 64 wave results through LDS
 // (ri: 2 MC_T / 64 ints).  Atomics of every lane to one LDS word were
 // compiled into a loop over the active lanes, some 900 scalar instructions
-// per wave, which dominated the set-up of a unit.
-__device__ __forceinline__ void block_minmax_i32(int &mn, int &mx, int *ri)
+// per wave, which dominated the set-up of a unit.  reuse: ri is written again
+// later in the unit (a second barrier keeps that write after every read).
+__device__ __forceinline__ void block_minmax_i32(int &mn, int &mx, int *ri, bool reuse = true)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -567,7 +568,7 @@ __device__ __forceinline__ void block_minmax_i32(int &mn, int &mx, int *ri)
         mn = mc_min(mn, ri[2 * w]);
         mx = mc_max(mx, ri[2 * w + 1]);
     }
-    __syncthreads();   // ri may be written again
+    if (reuse) __syncthreads();
 }
 
 // Reduce the GHR partials (or take the user range); every unit that calls
@@ -1049,7 +1050,7 @@ __device__ void hist_unit_v(const McVol &d, uint32_t wu, char *smem)
         if constexpr (VAL && !AHR) {
             // the unit's (min, max) value, for the global range of the clip
             // pass (+inf/-inf when the unit counted nothing)
-            block_minmax_i32(vmin, vmax, (int *)L.red);
+            block_minmax_i32(vmin, vmax, (int *)L.red, false);   // the unit's last use of LDS
             if (threadIdx.x == 0) {
                 d.rpart[2 * (int64_t)wu] = vmax >= 0 ? (float)vmin : INFINITY;
                 d.rpart[2 * (int64_t)wu + 1] = vmax >= 0 ? (float)vmax : -INFINITY;
@@ -1201,7 +1202,8 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
                     }
                 }
             }
-            block_minmax_i32(mn, mx, (int *)smem);
+            for (int i = threadIdx.x; i < nb; i += MC_T) hs[i] = 0u;
+            block_minmax_i32(mn, mx, (int *)smem, false);   // its barrier also orders the zeroing
             lo = o2f(mn);
             hi = o2f(mx);
         }
@@ -1217,8 +1219,10 @@ __device__ void clip_unit(const McVol &d, uint32_t k, char *smem)
                 d.scale[0] = sc;
             }
         }
-        for (int i = threadIdx.x; i < nb; i += MC_T) hs[i] = 0u;
-        __syncthreads();
+        if (d.mode == MC_GHR && d.has_user_range) {
+            for (int i = threadIdx.x; i < nb; i += MC_T) hs[i] = 0u;
+            __syncthreads();
+        }
         if (cnt) atomicAdd(&hs[bin_of((float)v, lo, sc, (float)nb, nb - 1)], cnt);
         __syncthreads();
     }
