@@ -682,13 +682,9 @@ def time_plan(torch, _lib, plan, x, dev, steps):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     p = timer.read()
-    # the same runs back to back, without events between the passes
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.run_ptr(*ptrs)
-    torch.cuda.synchronize()
-    ms_b2b = (time.perf_counter() - t0) / steps * 1e3
+    # the same runs back to back, without events between the passes (median
+    # of three repeats)
+    ms_b2b = steady_ms(torch, lambda: plan.run_ptr(*ptrs), steps, 3)[0]
     return ms, {k: round(p[k], 4) for k in ("range", "hist", "clip", "map")}, ms_b2b
 
 
