@@ -1535,9 +1535,10 @@ __device__ void map_unit_v(const McVol &d, uint32_t wu, char *smem)
     const bool vecst = (out_dt == MC_F32) && (V % 4 == 0) && allv;
     // the unit's row chunks, one after another on the same staged LUTs; the
     // outer-row table is rebuilt for each chunk
-    // (per-kernel range: one chunk per unit, which keeps its 2^D ranges in
-    // registers without spilling)
-    const int chA = chunk * d.mK, chB = AHR ? chA + 1 : mc_min(chA + d.mK, d.mCr);
+    // (under per-kernel ranges the unit's 2^D corner ranges stay in
+    // registers across its chunks too: each staging of 2^D LUTs, 32 KB at the
+    // 4D workload, then serves a whole cell instead of a fifth of one)
+    const int chA = chunk * d.mK, chB = mc_min(chA + d.mK, d.mCr);
     for (int ch = chA; ch < chB; ++ch) {
         const int64_t r0 = mc_div(rs.rows * ch, d.mCr), r1 = mc_div(rs.rows * (ch + 1), d.mCr);
         const int64_t o0 = mc_div(r0, rs.in_len);

@@ -402,8 +402,8 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
     const int64_t crmin_m = fast ? std::max<int64_t>(1, (omax_m + MC_OMAX - 5) / (MC_OMAX - 4)) : 1;
     // default row split: enough chunks for ~2048 units, but no chunk under
     // ~16K voxels (a unit's LUT staging dominates small ones); under a global
-    // range (where a unit runs several chunks on one LUT staging) also chunks
-    // of at most ~800 rows, the fastest measured at the 4D workload
+    // range also chunks of at most ~800 rows, the fastest measured at the 4D
+    // workload (a unit runs several chunks on one LUT staging)
     int64_t segw = 0;   // widest last-axis extent of a unit
     for (int cA = 0; cA < ncl; cA += mG) {
         int xs, xe, tmp;
@@ -424,7 +424,7 @@ static mclahe_status derive_core(const mclahe_plan_s *p, const mclahe_tuning &t,
     // per CU; fewer for a volume of a batch, whose units share the chip with
     // the others' and would otherwise stage their LUTs for few rows)
     int mk = 1;
-    if (fast && p->mode == MC_GHR) {
+    if (fast) {
         if (t.map_unit_chunks > 0) {
             mk = t.map_unit_chunks;
         } else {
